@@ -1,0 +1,433 @@
+/*
+ * CPU oracle for the CL-DIAM decomposition, quotient graph and diameter
+ * estimate.  TEST INFRASTRUCTURE ONLY: it exists to check the GPU library.
+ * Only the test suite, the smoke entry point and the benchmark's CPU-baseline
+ * leg may load it; the product path never does.
+ *
+ * Plain, sequential and slow on purpose.  It follows Ceccarello,
+ * Pietracaprina, Pucci, Upfal, "A practical parallel algorithm for diameter
+ * approximation of massive weighted graphs" (arXiv:1506.03265):
+ *   - decomposition: Algorithm 1 (CLUSTER) with the Delta-growing step and
+ *     Procedure Contract of Section 3;
+ *   - quotient graph and estimate: Section 4;
+ *   - single-source shortest paths for the Delta-stepping 2-approximation
+ *     baseline of Section 5 (exact distances, here by Dijkstra).
+ * It shares no code with the GPU library.
+ *
+ * Readings taken where the paper is silent or ambiguous (each one is pinned
+ * by a test against brute force or the mathematics):
+ *   log is log2; gamma = 4 ln 2; the stage loop runs while
+ *   |U| >= ceil(8 tau log2 n) and U is not empty; the selection probability is
+ *   p = ((gamma*tau)*log2 n)/|U| in IEEE double and node v of stage s is a new
+ *   center iff word 0 of Philox4x32-10(counter (v, s, 0, 0), key seed) is
+ *   below T = floor(p*2^32) (T = 2^32 when p >= 1).
+ *   PartialGrowth runs each Delta to its fixpoint; ties between equal
+ *   distances go to the smaller center id (lexicographic (d, c) minimum),
+ *   which is the fixpoint of repeated Delta-growing steps.
+ *   The contracted graph is not built: every node assigned in an earlier
+ *   stage acts as a source at distance 0 with its cluster's label, which is
+ *   what Contract's rewired edges (c_u, v) of weight w(u,v) provide.
+ *   Delta starts at floor(sum of weights / arcs) unless given, persists across
+ *   stages and doubles only while fewer than half of the uncovered nodes are
+ *   covered and some uncovered node is still reachable (otherwise the stage
+ *   keeps what it covered); Delta above 2^31 is an overflow error.
+ *   The distance recorded for a node assigned in stage s is
+ *   D = d + R_prev(c), where d is its stage-local growth distance and
+ *   R_prev(c) the radius bound of its cluster after stage s-1, so D bounds
+ *   dist(c, v) from above; the estimate is Phi(G_C) + 2 max D.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ENOMEM -2
+#define OR_EOVERFLOW -3
+#define OR_ESTAGES -4
+
+#define INF64 (~(uint64_t)0)
+#define DELTA_MAX ((uint64_t)1 << 31)
+#define MAX_STAGES 4096
+
+/* ------------------------------------------------- Philox4x32-10 (SC'11) -- */
+
+static void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int round = 0; round < 10; ++round) {
+    if (round) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint64_t a = (uint64_t)0xD2511F53u * c[0];
+    uint64_t b = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t x0 = (uint32_t)(b >> 32) ^ c[1] ^ k0;
+    uint32_t x2 = (uint32_t)(a >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)b;
+    c[3] = (uint32_t)a;
+    c[0] = x0;
+    c[2] = x2;
+  }
+}
+
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  philox4x32_10(c, key[0], key[1]);
+  memcpy(out, c, 16);
+}
+
+/* ------------------------------------------------------ binary min-heap -- */
+
+typedef struct { uint64_t d; uint32_t c; uint32_t v; } item_t;
+typedef struct { item_t *a; int64_t len, cap; } heap_t;
+
+static int less(const item_t *x, const item_t *y) {
+  return x->d < y->d || (x->d == y->d && x->c < y->c);
+}
+
+static int heap_push(heap_t *h, uint64_t d, uint32_t c, uint32_t v) {
+  if (h->len == h->cap) {
+    int64_t nc = h->cap ? 2 * h->cap : 1024;
+    item_t *na = realloc(h->a, (size_t)nc * sizeof(item_t));
+    if (!na) return -1;
+    h->a = na; h->cap = nc;
+  }
+  int64_t i = h->len++;
+  item_t it = {d, c, v};
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (!less(&it, &h->a[p])) break;
+    h->a[i] = h->a[p];
+    i = p;
+  }
+  h->a[i] = it;
+  return 0;
+}
+
+static item_t heap_pop(heap_t *h) {
+  item_t top = h->a[0], last = h->a[--h->len];
+  int64_t i = 0;
+  for (;;) {
+    int64_t l = 2 * i + 1, r = l + 1, s = i;
+    const item_t *cur = &last;
+    if (l < h->len && less(&h->a[l], cur)) { s = l; cur = &h->a[l]; }
+    if (r < h->len && less(&h->a[r], cur)) s = r;
+    if (s == i) break;
+    h->a[i] = h->a[s];
+    i = s;
+  }
+  if (h->len) h->a[i] = last;
+  return top;
+}
+
+/* ---------------------------------------------------------- decomposition -- */
+
+typedef struct {
+  int32_t stages;        /* executed stages of the outer loop */
+  int32_t levels;        /* PartialGrowth calls (one per Delta value tried) */
+  uint32_t delta0;
+  uint32_t delta_end;
+  int32_t stop;          /* ceil(8 tau log2 n) */
+  int32_t num_clusters;
+  int32_t singletons;
+  int32_t pad;
+  uint64_t radius;       /* max over nodes of D */
+  /* work counts of this sequential run, used for algorithmic bytes */
+  uint64_t sum_uncovered;  /* sum over stages of |U_s| */
+  uint64_t sum_acting;     /* nodes whose rows are read: settled + boundary sources */
+  uint64_t sum_arcs;       /* arcs read from those rows */
+  uint64_t sum_covered;    /* nodes assigned during stages */
+} or_stats;
+
+/* per-stage log, caller arrays of length log_cap (may be NULL) */
+typedef struct {
+  int32_t *uncovered;   /* |U_s| */
+  int32_t *centers;     /* new centers of stage s */
+  int32_t *covered;     /* nodes assigned in stage s (centers included) */
+  uint32_t *delta;      /* Delta in force when stage s assigned */
+  int32_t cap;
+} or_stage_log;
+
+uint32_t or_default_delta(int64_t m, const uint32_t *w) {
+  if (m <= 0) return 1;
+  uint64_t s = 0;
+  for (int64_t i = 0; i < m; ++i) s += w[i];
+  uint64_t d = s / (uint64_t)m;
+  return d < 1 ? 1u : (uint32_t)(d > 0xffffffffu ? 0xffffffffu : d);
+}
+
+int or_decompose(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                 uint32_t tau, uint32_t delta0, uint64_t seed,
+                 int32_t *cluster, uint64_t *D, or_stats *st, or_stage_log *lg) {
+  if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st) return OR_EINVAL;
+  memset(st, 0, sizeof *st);
+  int64_t m = row_ptr[n];
+  uint64_t delta = delta0 ? delta0 : or_default_delta(m, w);
+  st->delta0 = (uint32_t)delta;
+  if (delta > DELTA_MAX) return OR_EOVERFLOW;
+
+  const double gamma = 4.0 * M_LN2;
+  const double L = log2((double)n);
+  const int64_t stop = (int64_t)ceil(8.0 * tau * L);
+  st->stop = (int32_t)stop;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+
+  int32_t *U = malloc((size_t)n * 4);
+  int32_t *settled = malloc((size_t)n * 4);   /* stage stamp of settlement */
+  int32_t *srcmark = malloc((size_t)n * 4);   /* stage stamp of boundary sources */
+  uint32_t *loc = malloc((size_t)n * 4);
+  uint32_t *lab = malloc((size_t)n * 4);
+  uint64_t *R = calloc((size_t)n, 8);
+  int32_t *newly = malloc((size_t)n * 4);
+  heap_t h = {0};
+  int rc = OR_OK;
+  if (!U || !settled || !srcmark || !loc || !lab || !R || !newly) { rc = OR_ENOMEM; goto done; }
+  for (int32_t v = 0; v < n; ++v) { U[v] = v; cluster[v] = -1; D[v] = 0; settled[v] = -1; srcmark[v] = -1; }
+  int64_t nU = n;
+  int32_t s = 0;
+
+  while (nU > 0 && nU >= stop) {
+    if (s >= MAX_STAGES) { rc = OR_ESTAGES; goto done; }
+    /* new centers: each uncovered node independently with probability p */
+    double p = gamma * tau * L / (double)nU;
+    uint64_t T = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0);
+    h.len = 0;
+    int32_t ncent = 0;
+    for (int64_t i = 0; i < nU; ++i) {
+      uint32_t v = (uint32_t)U[i];
+      uint32_t c[4] = {v, (uint32_t)s, 0, 0};
+      philox4x32_10(c, k0, k1);
+      if ((uint64_t)c[0] < T) {
+        if (heap_push(&h, 0, v, v)) { rc = OR_ENOMEM; goto done; }
+        ncent++;
+      }
+    }
+    /* previously assigned nodes are sources at distance 0 (Contract); their
+     * first relaxations into U are generated from U's side */
+    for (int64_t i = 0; i < nU; ++i) {
+      int32_t v = U[i];
+      for (int32_t a = row_ptr[v]; a < row_ptr[v + 1]; ++a) {
+        int32_t u = col[a];
+        if (cluster[u] < 0) continue;
+        if (heap_push(&h, w[a], (uint32_t)cluster[u], (uint32_t)v)) { rc = OR_ENOMEM; goto done; }
+        if (srcmark[u] != s) {
+          srcmark[u] = s;
+          st->sum_acting++;
+          st->sum_arcs += (uint64_t)(row_ptr[u + 1] - row_ptr[u]);
+        }
+      }
+    }
+    int64_t covered = 0;
+    int32_t nnew = 0;
+    /* PartialGrowth(Delta) to its fixpoint = lexicographic Dijkstra limited to
+     * distance <= Delta; entries beyond Delta stay queued for a larger Delta */
+    for (;;) {
+      st->levels++;
+      while (h.len && h.a[0].d <= delta) {
+        item_t it = heap_pop(&h);
+        if (settled[it.v] == s) continue;
+        settled[it.v] = s;
+        loc[it.v] = (uint32_t)it.d;
+        lab[it.v] = it.c;
+        newly[nnew++] = (int32_t)it.v;
+        covered++;
+        st->sum_acting++;
+        st->sum_arcs += (uint64_t)(row_ptr[it.v + 1] - row_ptr[it.v]);
+        for (int32_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
+          int32_t x = col[a];
+          if (cluster[x] >= 0 || settled[x] == s) continue;
+          if (heap_push(&h, it.d + w[a], it.c, (uint32_t)x)) { rc = OR_ENOMEM; goto done; }
+        }
+      }
+      while (h.len && settled[h.a[0].v] == s) heap_pop(&h);
+      if (2 * covered >= nU) break;   /* at least half of U covered */
+      if (h.len == 0) break;          /* no uncovered node reachable at any Delta */
+      if (2 * delta > DELTA_MAX) { rc = OR_EOVERFLOW; goto done; }
+      delta *= 2;
+    }
+    /* assign: D from the radius bounds of the previous stage, then update */
+    for (int32_t i = 0; i < nnew; ++i) {
+      int32_t v = newly[i];
+      cluster[v] = (int32_t)lab[v];
+      D[v] = (uint64_t)loc[v] + R[lab[v]];
+    }
+    for (int32_t i = 0; i < nnew; ++i) {
+      int32_t v = newly[i];
+      if (D[v] > R[lab[v]]) R[lab[v]] = D[v];
+    }
+    if (lg && s < lg->cap) {
+      if (lg->uncovered) lg->uncovered[s] = (int32_t)nU;
+      if (lg->centers) lg->centers[s] = ncent;
+      if (lg->covered) lg->covered[s] = nnew;
+      if (lg->delta) lg->delta[s] = (uint32_t)delta;
+    }
+    st->sum_uncovered += (uint64_t)nU;
+    st->sum_covered += (uint64_t)nnew;
+    int64_t k = 0;
+    for (int64_t i = 0; i < nU; ++i)
+      if (cluster[U[i]] < 0) U[k++] = U[i];
+    nU = k;
+    s++;
+  }
+  /* the few nodes left become singleton clusters */
+  for (int64_t i = 0; i < nU; ++i) { cluster[U[i]] = U[i]; D[U[i]] = 0; }
+  st->singletons = (int32_t)nU;
+  st->stages = s;
+  st->delta_end = (uint32_t)delta;
+  for (int32_t v = 0; v < n; ++v) {
+    if (cluster[v] == v) st->num_clusters++;
+    if (D[v] > st->radius) st->radius = D[v];
+  }
+done:
+  free(U); free(settled); free(srcmark); free(loc); free(lab); free(R); free(newly); free(h.a);
+  return rc;
+}
+
+/* ------------------------------------------------------------ quotient -- */
+
+typedef struct { uint64_t key; uint64_t w; } qrec_t;
+
+static int cmp_qrec(const void *a, const void *b) {
+  const qrec_t *x = a, *y = b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->w < y->w ? -1 : (x->w > y->w);
+}
+
+/* Weighted quotient graph (Section 4): one node per cluster, numbered by
+ * ascending center id; for every edge (u,v) with c_u != c_v an edge between
+ * the two clusters of weight w(u,v) + D_u + D_v, keeping the lightest of
+ * parallel edges.  Outputs:
+ *   k, center[k]            cluster index -> center node id
+ *   ne, ea[ne], eb[ne], ew[ne]  undirected edges a < b, sorted by (a, b)
+ * Arrays are malloc'd here and freed with or_free. */
+int or_quotient(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                const int32_t *cluster, const uint64_t *D,
+                int32_t *k_out, int32_t **center_out, int64_t *ne_out,
+                int32_t **ea_out, int32_t **eb_out, uint64_t **ew_out, int64_t *pairs_out) {
+  int32_t *dense = malloc((size_t)n * 4);
+  if (!dense) return OR_ENOMEM;
+  int32_t k = 0;
+  for (int32_t v = 0; v < n; ++v) dense[v] = (cluster[v] == v) ? k++ : -1;
+  int32_t *center = malloc((size_t)(k ? k : 1) * 4);
+  int64_t P = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
+      if (u < col[a] && cluster[u] != cluster[col[a]]) P++;
+  qrec_t *rec = malloc((size_t)(P ? P : 1) * sizeof(qrec_t));
+  if (!center || !rec) { free(dense); free(center); free(rec); return OR_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v)
+    if (dense[v] >= 0) center[dense[v]] = v;
+  int64_t i = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+      int32_t v = col[a];
+      if (!(u < v) || cluster[u] == cluster[v]) continue;
+      uint64_t x = (uint64_t)dense[cluster[u]], y = (uint64_t)dense[cluster[v]];
+      if (x > y) { uint64_t t = x; x = y; y = t; }
+      rec[i].key = (x << 32) | y;
+      rec[i].w = (uint64_t)w[a] + D[u] + D[v];
+      i++;
+    }
+  qsort(rec, (size_t)P, sizeof(qrec_t), cmp_qrec);
+  int64_t ne = 0;
+  for (int64_t j = 0; j < P; ++j)
+    if (j == 0 || rec[j].key != rec[j - 1].key) ne++;
+  int32_t *ea = malloc((size_t)(ne ? ne : 1) * 4), *eb = malloc((size_t)(ne ? ne : 1) * 4);
+  uint64_t *ew = malloc((size_t)(ne ? ne : 1) * 8);
+  if (!ea || !eb || !ew) { free(dense); free(center); free(rec); free(ea); free(eb); free(ew); return OR_ENOMEM; }
+  int64_t e = 0;
+  for (int64_t j = 0; j < P; ++j)
+    if (j == 0 || rec[j].key != rec[j - 1].key) {
+      ea[e] = (int32_t)(rec[j].key >> 32);
+      eb[e] = (int32_t)(rec[j].key & 0xffffffffu);
+      ew[e] = rec[j].w;   /* first of its run = minimum weight */
+      e++;
+    }
+  free(rec); free(dense);
+  *k_out = k; *center_out = center; *ne_out = ne; *ea_out = ea; *eb_out = eb; *ew_out = ew;
+  if (pairs_out) *pairs_out = P;
+  return OR_OK;
+}
+
+void or_free(void *p) { free(p); }
+
+/* ---------------------------------------------------- shortest paths -- */
+
+/* Dijkstra from src over a CSR with u64 weights; dist[v] = INF64 when
+ * unreachable. */
+static int dijkstra64(int32_t n, const int64_t *rp, const int32_t *col, const uint64_t *w, int32_t src,
+                      uint64_t *dist, heap_t *h) {
+  for (int32_t v = 0; v < n; ++v) dist[v] = INF64;
+  h->len = 0;
+  dist[src] = 0;
+  if (heap_push(h, 0, 0, (uint32_t)src)) return OR_ENOMEM;
+  while (h->len) {
+    item_t it = heap_pop(h);
+    if (it.d != dist[it.v]) continue;
+    for (int64_t a = rp[it.v]; a < rp[it.v + 1]; ++a) {
+      uint64_t nd = it.d + w[a];
+      if (nd < dist[col[a]]) {
+        dist[col[a]] = nd;
+        if (heap_push(h, nd, 0, (uint32_t)col[a])) return OR_ENOMEM;
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* Exact weighted diameter of an undirected graph given as an edge list over
+ * k nodes: max finite distance over all pairs, one Dijkstra per node. */
+int or_diameter_edges(int32_t k, int64_t ne, const int32_t *ea, const int32_t *eb, const uint64_t *ew,
+                      uint64_t *phi_out) {
+  int64_t *rp = calloc((size_t)k + 1, 8);
+  int32_t *col = malloc((size_t)(2 * ne + 1) * 4);
+  uint64_t *ww = malloc((size_t)(2 * ne + 1) * 8);
+  int64_t *cur = malloc(((size_t)k + 1) * 8);
+  uint64_t *dist = malloc(((size_t)k + 1) * 8);
+  heap_t h = {0};
+  int rc = OR_OK;
+  if (!rp || !col || !ww || !cur || !dist) { rc = OR_ENOMEM; goto out; }
+  for (int64_t e = 0; e < ne; ++e) { rp[ea[e] + 1]++; rp[eb[e] + 1]++; }
+  for (int32_t v = 0; v < k; ++v) rp[v + 1] += rp[v];
+  memcpy(cur, rp, (size_t)k * 8);
+  for (int64_t e = 0; e < ne; ++e) {
+    col[cur[ea[e]]] = eb[e]; ww[cur[ea[e]]++] = ew[e];
+    col[cur[eb[e]]] = ea[e]; ww[cur[eb[e]]++] = ew[e];
+  }
+  uint64_t phi = 0;
+  for (int32_t s = 0; s < k; ++s) {
+    if ((rc = dijkstra64(k, rp, col, ww, s, dist, &h))) goto out;
+    for (int32_t v = 0; v < k; ++v)
+      if (dist[v] != INF64 && dist[v] > phi) phi = dist[v];
+  }
+  *phi_out = phi;
+out:
+  free(rp); free(col); free(ww); free(cur); free(dist); free(h.a);
+  return rc;
+}
+
+/* Single-source shortest paths on the input graph (the exact distances that
+ * Delta-stepping computes).  dist is u32 with 0xFFFFFFFF for unreachable;
+ * a finite distance that does not fit below that value is an overflow. */
+int or_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t src,
+            uint32_t *dist_out, uint64_t *max_out) {
+  if (src < 0 || src >= n) return OR_EINVAL;
+  int64_t m = row_ptr[n];
+  int64_t *rp = malloc(((size_t)n + 1) * 8);
+  uint64_t *ww = malloc((size_t)(m ? m : 1) * 8);
+  uint64_t *dist = malloc((size_t)n * 8);
+  heap_t h = {0};
+  int rc = OR_OK;
+  if (!rp || !ww || !dist) { rc = OR_ENOMEM; goto out; }
+  for (int32_t v = 0; v <= n; ++v) rp[v] = row_ptr[v];
+  for (int64_t a = 0; a < m; ++a) ww[a] = w[a];
+  if ((rc = dijkstra64(n, rp, col, ww, src, dist, &h))) goto out;
+  uint64_t mx = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    if (dist[v] == INF64) { dist_out[v] = 0xffffffffu; continue; }
+    if (dist[v] >= 0xffffffffu) { rc = OR_EOVERFLOW; goto out; }
+    dist_out[v] = (uint32_t)dist[v];
+    if (dist[v] > mx) mx = dist[v];
+  }
+  *max_out = mx;
+out:
+  free(rp); free(ww); free(dist); free(h.a);
+  return rc;
+}
