@@ -1,0 +1,210 @@
+/*
+ * cldiam.h - C ABI of libcldiam.so, the MI355X (gfx950) implementation of the
+ * CL-DIAM diameter approximation of Ceccarello, Pietracaprina, Pucci, Upfal,
+ * "A practical parallel algorithm for diameter approximation of massive
+ * weighted graphs" (arXiv:1506.03265).
+ *
+ * Conventions shared by every entry point
+ *   - Graphs are undirected, with positive integer edge weights (Section 2).
+ *     They are passed as a symmetric CSR: every edge {u,v} appears as the two
+ *     arcs u->v and v->u with the same weight; each row is sorted by strictly
+ *     increasing column; there are no self loops.
+ *   - Every pointer named d_* is DEVICE memory on the current HIP device and is
+ *     owned by the caller.  Every pointer named h_* is HOST memory.  The library
+ *     allocates no device memory: scratch comes from a caller workspace `ws` of
+ *     at least the size returned by the matching *_workspace_size query, aligned
+ *     to 256 bytes.  The workspace may be reused between calls but not shared
+ *     by calls that run at the same time.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every entry point
+ *     enqueues its work on that stream and returns after it has completed
+ *     (the decomposition steers itself from values it reads back), so outputs
+ *     are ready when the call returns.
+ *   - Return value: CLDIAM_OK (0) or a negative status below.  On error the
+ *     outputs are unspecified; cldiam_last_error() gives a message for the
+ *     calling thread.  No exception or signal crosses the ABI.
+ *   - All arithmetic is integer; results are deterministic and bit-identical
+ *     to a sequential execution of the method.
+ *   - Entry points may be called from several host threads at once on
+ *     different streams and workspaces.
+ */
+#ifndef CLDIAM_H
+#define CLDIAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLDIAM_OK 0
+#define CLDIAM_EINVAL (-1)     /* bad argument or malformed CSR */
+#define CLDIAM_ENOMEM (-2)     /* workspace too small */
+#define CLDIAM_EOVERFLOW (-3)  /* Delta would exceed 2^31, or a u32 distance would overflow */
+#define CLDIAM_EHIP (-4)       /* HIP runtime error */
+#define CLDIAM_ESTAGES (-5)    /* more than CLDIAM_MAX_STAGES stages */
+#define CLDIAM_ETIMEOUT (-6)   /* a device-side wait exceeded its time limit */
+
+#define CLDIAM_MAX_STAGES 4096
+#define CLDIAM_STAGE_LOG 64
+
+/* Human-readable name of a status code (static string). */
+const char *cldiam_strerror(int status);
+/* Detail of the last error on the calling thread (static per thread). */
+const char *cldiam_last_error(void);
+/* Library version string. */
+const char *cldiam_version(void);
+
+/* Device CSR of one graph (all DEVICE pointers, caller-owned).
+ * n >= 1 nodes, m arcs (m = 2 x edges, m < 2^31). */
+typedef struct {
+  int32_t n;
+  int32_t pad;
+  int64_t m;
+  const int32_t *d_row_ptr; /* n+1 offsets, d_row_ptr[0] = 0, d_row_ptr[n] = m */
+  const int32_t *d_col;     /* m column ids in [0, n) */
+  const uint32_t *d_w;      /* m weights >= 1 */
+} cldiam_csr;
+
+/* ------------------------------------------------------------- ingest ---
+ * Validates a CSR (symmetric with equal weights, columns in range and
+ * strictly increasing per row, no self loops, weights >= 1) and packs its arcs
+ * as d_arcs[a] = (uint64_t)w << 32 | col with every row re-sorted by
+ * (weight, column).  Light arcs (w <= Delta, Section 3) of a row are then a
+ * prefix of that row.  The packed arcs are the graph operand of every other
+ * entry point.  Also returns the sum of all arc weights (for the default
+ * initial Delta).  Returns CLDIAM_EINVAL if validation fails. */
+size_t cldiam_load_csr_workspace_size(int32_t n, int64_t m);
+int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *h_weight_sum, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* ------------------------------------------------------ decomposition ---
+ * CLUSTER(G, tau) of Algorithm 1 (Section 3): stages that draw random new
+ * centers among uncovered nodes, grow all clusters by Delta-growing steps
+ * (light-edge relaxation bounded by Delta) until at least half of the
+ * uncovered nodes are covered, doubling Delta when needed, and finally make
+ * the few remaining nodes singleton clusters.
+ *
+ * Precise behaviour (the readings of the paper this library implements):
+ *   - log is log2, gamma = 4 ln 2; stages run while the uncovered count U is
+ *     at least ceil(8 tau log2 n) (and n > 1, U > 0);
+ *   - in stage s (from 0) node v is a new center iff word 0 of
+ *     Philox4x32-10(counter = (v, s, 0, 0), key = (seed lo, seed hi)) is below
+ *     T = floor(p 2^32), p = ((gamma tau) log2 n) / U in IEEE double
+ *     (T = 2^32 when p >= 1);
+ *   - growth runs every Delta to its fixpoint; a node keeps the lexicographic
+ *     minimum (distance, center id) over all offers; nodes assigned in earlier
+ *     stages act as sources at distance 0 with their cluster's label, which is
+ *     Procedure Contract's effect;
+ *   - Delta starts at delta0 (0 = floor(sum of arc weights / m), at least 1),
+ *     persists across stages, and doubles while fewer than half of U is
+ *     covered and some uncovered node is still reachable; Delta above 2^31 is
+ *     CLDIAM_EOVERFLOW;
+ *   - a node assigned in stage s with growth distance d to cluster c gets
+ *     D = d + R(c), R(c) being the largest D in c after stage s-1; so D is an
+ *     upper bound on the distance from the center, and max D is the
+ *     clustering radius bound used by the estimate.
+ * Outputs: d_cluster[v] = center node id of v's cluster (a center has
+ * d_cluster[c] = c); d_D[v] as above. */
+typedef struct {
+  uint32_t tau;    /* >= 1 */
+  uint32_t delta0; /* initial Delta; 0 = floor(sum of arc weights / m) */
+  uint64_t seed;   /* Philox key */
+} cldiam_params;
+
+typedef struct {
+  int32_t stages;       /* executed stages */
+  int32_t levels;       /* Delta values tried (growth to fixpoint per value) */
+  uint32_t delta0;      /* initial Delta used */
+  uint32_t delta_end;   /* Delta at the end */
+  int32_t stop;         /* ceil(8 tau log2 n) */
+  int32_t num_clusters; /* centers drawn + singletons */
+  int32_t singletons;
+  int32_t sweeps;       /* device relaxation sweeps (schedule dependent) */
+  uint64_t radius;      /* max over nodes of D */
+  uint64_t arcs_scanned;/* arcs read by relaxation (schedule dependent) */
+  int32_t status;       /* per-graph status (CLDIAM_OK or an error) */
+  int32_t pad;
+  /* per stage s < min(stages, CLDIAM_STAGE_LOG) */
+  int32_t stage_uncovered[CLDIAM_STAGE_LOG];
+  int32_t stage_centers[CLDIAM_STAGE_LOG];
+  int32_t stage_covered[CLDIAM_STAGE_LOG];
+  uint32_t stage_delta[CLDIAM_STAGE_LOG];
+} cldiam_stats;
+
+/* Driver of the device-side control loop. */
+#define CLDIAM_DRIVER_AUTO 0       /* persistent kernel when the device allows it */
+#define CLDIAM_DRIVER_HOST 1       /* one launch per sweep, host polls */
+#define CLDIAM_DRIVER_PERSISTENT 2 /* one cooperative launch for the whole job */
+
+/* One graph description of a batch (graph operand in DEVICE memory). */
+typedef struct {
+  int32_t n;
+  int32_t pad;
+  int64_t m;
+  const int32_t *d_row_ptr; /* n+1 */
+  const uint64_t *d_arcs;   /* m packed arcs from cldiam_load_csr */
+  uint64_t weight_sum;      /* sum of arc weights (cldiam_load_csr) */
+  cldiam_params params;
+  int32_t *d_cluster;       /* out, n */
+  uint64_t *d_D;            /* out, n */
+} cldiam_graph;
+
+/* Workspace for a batch whose node counts sum to total_n (over num_graphs). */
+size_t cldiam_decompose_workspace_size(int64_t total_n, int32_t num_graphs);
+
+/* Decomposes num_graphs independent graphs in one device job; per-graph
+ * results equal those of separate single-graph calls.  h_stats (host,
+ * num_graphs entries, may be NULL) receives per-graph statistics.
+ * driver: one of CLDIAM_DRIVER_*.  A failure of one graph is reported in its
+ * stats status and as the return value (the first failing graph's status). */
+int cldiam_decompose_batch(int32_t num_graphs, const cldiam_graph *h_graphs, cldiam_stats *h_stats, int driver,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Single-graph convenience form of cldiam_decompose_batch. */
+int cldiam_decompose(const cldiam_graph *h_graph, cldiam_stats *h_stats, int driver, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* ---------------------------------------------------- quotient graph ---
+ * Weighted quotient graph G_C of Section 4: one node per cluster, numbered by
+ * ascending center id; for every edge {u,v} of G with c_u != c_v an edge
+ * between their clusters of weight w(u,v) + D_u + D_v; of parallel edges only
+ * the lightest is kept.  Outputs (DEVICE, caller-sized for the worst case):
+ *   d_qcenter[k]      center node id of quotient node i (ascending)
+ *   d_qrow_ptr[k+1]   symmetric CSR offsets (int64), rows sorted by column
+ *   d_qcol[<= m]      quotient neighbours
+ *   d_qw[<= m]        quotient weights (u64)
+ * and on the host *h_k = k and *h_qm = number of quotient arcs (2 x edges).
+ * Arrays sized n+1 (row_ptr), n (center) and m (col, w) always suffice. */
+size_t cldiam_quotient_workspace_size(int32_t n, int64_t m);
+int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+                          const int32_t *d_cluster, const uint64_t *d_D, int32_t *d_qcenter, int64_t *d_qrow_ptr,
+                          int32_t *d_qcol, uint64_t *d_qw, int32_t *h_k, int64_t *h_qm, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* ---------------------------------------------------------- estimate ---
+ * Phi(G_C) = exact largest finite shortest-path distance between two nodes of
+ * the quotient graph (k nodes, symmetric CSR from cldiam_build_quotient), and
+ * Phi_approx = Phi(G_C) + 2 radius, the conservative estimate of Section 4
+ * (radius = max D of the decomposition).  Results on the host. */
+size_t cldiam_estimate_workspace_size(int32_t k, int64_t qm);
+int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, const int32_t *d_qcol,
+                             const uint64_t *d_qw, uint64_t radius, uint64_t *h_phi_gc, uint64_t *h_phi_approx,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------ SSSP (the competitor) ---
+ * Delta-stepping single-source shortest paths (Meyer and Sanders), the
+ * baseline of Section 5: twice the largest finite distance from one source is
+ * a 2-approximation of the diameter.  d_dist[v] receives the exact distance
+ * (0xFFFFFFFF = unreachable); *h_max_dist the largest finite one.
+ * bucket_delta = 0 picks the default width (the mean arc weight).  A finite
+ * distance >= 0xFFFFFFFF returns CLDIAM_EOVERFLOW. */
+size_t cldiam_sssp_workspace_size(int32_t n, int64_t m);
+int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+                               int32_t source, uint32_t bucket_delta, uint32_t *d_dist, uint64_t *h_max_dist,
+                               void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLDIAM_H */

@@ -118,7 +118,7 @@ def cluster(n, edges, tau, seed, delta0=0, mode="apsp"):
     levels = 0
     while True:
         U = sorted(Vi - Ci)
-        if not U or len(U) < stop:
+        if n < 2 or not U or len(U) < stop:
             break
         p = gamma * tau * L / len(U)
         T = (1 << 32) if p >= 1.0 else math.floor(p * 4294967296.0)

@@ -17,7 +17,8 @@
  * Readings taken where the paper is silent or ambiguous (each one is pinned
  * by a test against brute force or the mathematics):
  *   log is log2; gamma = 4 ln 2; the stage loop runs while
- *   |U| >= ceil(8 tau log2 n) and U is not empty; the selection probability is
+ *   |U| >= ceil(8 tau log2 n), U is not empty and n > 1 (a single node,
+ *   where log2 n = 0 makes the selection probability 0, is its own cluster); the selection probability is
  *   p = ((gamma*tau)*log2 n)/|U| in IEEE double and node v of stage s is a new
  *   center iff word 0 of Philox4x32-10(counter (v, s, 0, 0), key seed) is
  *   below T = floor(p*2^32) (T = 2^32 when p >= 1).
@@ -183,7 +184,7 @@ int or_decompose(int32_t n, const int32_t *row_ptr, const int32_t *col, const ui
   int64_t nU = n;
   int32_t s = 0;
 
-  while (nU > 0 && nU >= stop) {
+  while (n > 1 && nU > 0 && nU >= stop) {
     if (s >= MAX_STAGES) { rc = OR_ESTAGES; goto done; }
     /* new centers: each uncovered node independently with probability p */
     double p = gamma * tau * L / (double)nU;

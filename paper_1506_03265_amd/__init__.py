@@ -1,0 +1,367 @@
+"""Python binding of libcldiam.so, the gfx950 implementation of the CL-DIAM
+decomposition, quotient graph and diameter estimate (arXiv:1506.03265).
+
+The functions have the names of the C entry points in include/cldiam.h and
+only marshal arguments: PyTorch provides device memory and the stream, every
+step of the computation runs in the library's HIP kernels.  Importing works
+anywhere; calling needs the built library (``paper_1506_03265_amd/build.py``)
+and a GPU, otherwise a RuntimeError is raised.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcldiam.so")
+
+CLDIAM_OK = 0
+CLDIAM_EINVAL = -1
+CLDIAM_ENOMEM = -2
+CLDIAM_EOVERFLOW = -3
+CLDIAM_EHIP = -4
+CLDIAM_ESTAGES = -5
+CLDIAM_ETIMEOUT = -6
+STAGE_LOG = 64
+
+DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
+
+EXPORTS = [
+    "cldiam_strerror", "cldiam_last_error", "cldiam_version",
+    "cldiam_load_csr_workspace_size", "cldiam_load_csr",
+    "cldiam_decompose_workspace_size", "cldiam_decompose_batch", "cldiam_decompose",
+    "cldiam_quotient_workspace_size", "cldiam_build_quotient",
+    "cldiam_estimate_workspace_size", "cldiam_estimate_diameter",
+    "cldiam_sssp_workspace_size", "cldiam_sssp_delta_stepping",
+]
+
+
+class CldiamError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: status {status} ({detail})")
+        self.status = status
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pad", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("d_row_ptr", ctypes.c_void_p), ("d_col", ctypes.c_void_p), ("d_w", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_uint32), ("delta0", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pad", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("d_row_ptr", ctypes.c_void_p), ("d_arcs", ctypes.c_void_p), ("weight_sum", ctypes.c_uint64),
+                ("params", _Params), ("d_cluster", ctypes.c_void_p), ("d_D", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("levels", ctypes.c_int32), ("delta0", ctypes.c_uint32),
+                ("delta_end", ctypes.c_uint32), ("stop", ctypes.c_int32), ("num_clusters", ctypes.c_int32),
+                ("singletons", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("radius", ctypes.c_uint64),
+                ("arcs_scanned", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("stage_uncovered", ctypes.c_int32 * STAGE_LOG), ("stage_centers", ctypes.c_int32 * STAGE_LOG),
+                ("stage_covered", ctypes.c_int32 * STAGE_LOG), ("stage_delta", ctypes.c_uint32 * STAGE_LOG)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libcldiam.so and declares every exported signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_1506_03265_amd/build.py (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    V, I32, I64, U32, U64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                 ctypes.c_uint64, ctypes.c_size_t)
+    P = ctypes.POINTER
+    lib.cldiam_strerror.argtypes, lib.cldiam_strerror.restype = [ctypes.c_int], ctypes.c_char_p
+    lib.cldiam_last_error.argtypes, lib.cldiam_last_error.restype = [], ctypes.c_char_p
+    lib.cldiam_version.argtypes, lib.cldiam_version.restype = [], ctypes.c_char_p
+    lib.cldiam_load_csr_workspace_size.argtypes, lib.cldiam_load_csr_workspace_size.restype = [I32, I64], SZ
+    lib.cldiam_load_csr.argtypes = [P(_Csr), V, P(U64), V, SZ, V]
+    lib.cldiam_decompose_workspace_size.argtypes, lib.cldiam_decompose_workspace_size.restype = [I64, I32], SZ
+    lib.cldiam_decompose_batch.argtypes = [I32, P(_Graph), P(_Stats), ctypes.c_int, V, SZ, V]
+    lib.cldiam_decompose.argtypes = [P(_Graph), P(_Stats), ctypes.c_int, V, SZ, V]
+    lib.cldiam_quotient_workspace_size.argtypes, lib.cldiam_quotient_workspace_size.restype = [I32, I64], SZ
+    lib.cldiam_build_quotient.argtypes = [I32, I64, V, V, V, V, V, V, V, V, P(I32), P(I64), V, SZ, V]
+    lib.cldiam_estimate_workspace_size.argtypes, lib.cldiam_estimate_workspace_size.restype = [I32, I64], SZ
+    lib.cldiam_estimate_diameter.argtypes = [I32, I64, V, V, V, U64, P(U64), P(U64), V, SZ, V]
+    lib.cldiam_sssp_workspace_size.argtypes, lib.cldiam_sssp_workspace_size.restype = [I32, I64], SZ
+    lib.cldiam_sssp_delta_stepping.argtypes = [I32, I64, V, V, I32, U32, V, P(U64), V, SZ, V]
+    for name in ("cldiam_load_csr", "cldiam_decompose_batch", "cldiam_decompose", "cldiam_build_quotient",
+                 "cldiam_estimate_diameter", "cldiam_sssp_delta_stepping"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != CLDIAM_OK:
+        lib = load_library()
+        detail = lib.cldiam_last_error().decode(errors="replace")
+        raise CldiamError(rc, what, detail)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libcldiam needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ws(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+# ------------------------------------------------------------------ ingest --
+
+@dataclass
+class DeviceGraph:
+    """Graph resident in device memory: CSR plus weight-sorted packed arcs."""
+    n: int
+    m: int
+    row_ptr: object      # torch int32 [n+1]
+    col: object          # torch int32 [m]
+    w: object            # torch int32 [m] (bit pattern of uint32)
+    arcs: object         # torch int64 [m] (bit pattern of (w << 32) | col)
+    weight_sum: int
+    name: str = ""
+
+
+def to_device(g, device="cuda"):
+    """Copies a host CSR (graphgen.Graph) to device tensors (no validation)."""
+    torch = _torch()
+    rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(device)
+    w = torch.from_numpy(np.ascontiguousarray(g.w, dtype=np.uint32).view(np.int32)).to(device)
+    return rp, col, w
+
+
+def cldiam_load_csr(g, device="cuda", stream=None) -> DeviceGraph:
+    """Uploads a host CSR and runs cldiam_load_csr (validation + weight-sorted
+    packed arcs)."""
+    torch = _torch()
+    lib = load_library()
+    rp, col, w = to_device(g, device)
+    n, m = int(g.n), int(len(g.col))
+    arcs = torch.empty(max(m, 1), dtype=torch.int64, device=device)
+    csr = _Csr(n, 0, m, rp.data_ptr(), _ptr(col).value, _ptr(w).value)
+    wsb = lib.cldiam_load_csr_workspace_size(n, m)
+    ws = _ws(wsb, device)
+    wsum = ctypes.c_uint64()
+    _check(lib.cldiam_load_csr(ctypes.byref(csr), _ptr(arcs), ctypes.byref(wsum), _ptr(ws), wsb, _stream(stream)),
+           "cldiam_load_csr")
+    return DeviceGraph(n, m, rp, col, w, arcs, int(wsum.value), getattr(g, "name", ""))
+
+
+def cldiam_load_csr_device(n, m, rp, col, w, stream=None) -> DeviceGraph:
+    """cldiam_load_csr on tensors already on the device."""
+    torch = _torch()
+    lib = load_library()
+    arcs = torch.empty(max(m, 1), dtype=torch.int64, device=rp.device)
+    csr = _Csr(n, 0, m, rp.data_ptr(), _ptr(col).value, _ptr(w).value)
+    wsb = lib.cldiam_load_csr_workspace_size(n, m)
+    ws = _ws(wsb, rp.device)
+    wsum = ctypes.c_uint64()
+    _check(lib.cldiam_load_csr(ctypes.byref(csr), _ptr(arcs), ctypes.byref(wsum), _ptr(ws), wsb, _stream(stream)),
+           "cldiam_load_csr")
+    return DeviceGraph(n, m, rp, col, w, arcs, int(wsum.value))
+
+
+# ------------------------------------------------------------ decompose --
+
+@dataclass
+class Stats:
+    stages: int
+    levels: int
+    delta0: int
+    delta_end: int
+    stop: int
+    num_clusters: int
+    singletons: int
+    sweeps: int
+    radius: int
+    arcs_scanned: int
+    status: int
+    stage_uncovered: list = field(default_factory=list)
+    stage_centers: list = field(default_factory=list)
+    stage_covered: list = field(default_factory=list)
+    stage_delta: list = field(default_factory=list)
+
+
+def _stats(s: _Stats) -> Stats:
+    k = min(s.stages, STAGE_LOG)
+    return Stats(s.stages, s.levels, s.delta0, s.delta_end, s.stop, s.num_clusters, s.singletons, s.sweeps,
+                 int(s.radius), int(s.arcs_scanned), s.status, list(s.stage_uncovered[:k]),
+                 list(s.stage_centers[:k]), list(s.stage_covered[:k]), list(s.stage_delta[:k]))
+
+
+class DecomposeJob:
+    """Reusable decomposition launch: outputs, workspace and descriptors are
+    allocated once so that repeated runs time only the device work."""
+
+    def __init__(self, graphs, params, driver=DRIVER_AUTO):
+        torch = _torch()
+        self.lib = load_library()
+        self.graphs = list(graphs)
+        dev = self.graphs[0].row_ptr.device
+        self.cluster = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in self.graphs]
+        self.D = [torch.empty(g.n, dtype=torch.int64, device=dev) for g in self.graphs]
+        G = len(self.graphs)
+        self.desc = (_Graph * G)()
+        for i, (g, p) in enumerate(zip(self.graphs, params)):
+            tau, seed, delta0 = p
+            self.desc[i] = _Graph(g.n, 0, g.m, g.row_ptr.data_ptr(), _ptr(g.arcs).value, g.weight_sum,
+                                  _Params(tau, delta0, seed), self.cluster[i].data_ptr(), self.D[i].data_ptr())
+        self.stats = (_Stats * G)()
+        total_n = sum(g.n for g in self.graphs)
+        self.wsb = self.lib.cldiam_decompose_workspace_size(total_n, G)
+        self.ws = _ws(self.wsb, dev)
+        self.driver = driver
+
+    def run(self, stream=None):
+        _check(self.lib.cldiam_decompose_batch(len(self.graphs), self.desc, self.stats, self.driver, _ptr(self.ws),
+                                               self.wsb, _stream(stream)), "cldiam_decompose_batch")
+        return [_stats(s) for s in self.stats]
+
+
+def cldiam_decompose(g: DeviceGraph, tau: int, seed: int, delta0: int = 0, driver=DRIVER_AUTO, stream=None):
+    """CLUSTER(G, tau): returns (cluster int32 tensor, D int64 tensor holding
+    uint64 bit patterns, Stats)."""
+    job = DecomposeJob([g], [(tau, seed, delta0)], driver)
+    st = job.run(stream)
+    return job.cluster[0], job.D[0], st[0]
+
+
+def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None):
+    """Decomposes many graphs in one device job; params = [(tau, seed, delta0)]."""
+    job = DecomposeJob(graphs, params, driver)
+    st = job.run(stream)
+    return job.cluster, job.D, st
+
+
+# ------------------------------------------------------------- quotient --
+
+@dataclass
+class DeviceQuotient:
+    k: int
+    qm: int
+    center: object    # torch int32 [k]
+    row_ptr: object   # torch int64 [k+1]
+    col: object       # torch int32 [qm]
+    w: object         # torch int64 [qm] (uint64 bit patterns)
+
+
+class QuotientJob:
+    def __init__(self, g: DeviceGraph):
+        torch = _torch()
+        self.lib = load_library()
+        self.g = g
+        dev = g.row_ptr.device
+        self.center = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+        self.row_ptr = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+        self.col = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+        self.w = torch.empty(max(g.m, 1), dtype=torch.int64, device=dev)
+        self.wsb = self.lib.cldiam_quotient_workspace_size(g.n, g.m)
+        self.ws = _ws(self.wsb, dev)
+
+    def run(self, cluster, D, stream=None) -> DeviceQuotient:
+        k, qm = ctypes.c_int32(), ctypes.c_int64()
+        g = self.g
+        _check(self.lib.cldiam_build_quotient(g.n, g.m, _ptr(g.row_ptr), _ptr(g.arcs), _ptr(cluster), _ptr(D),
+                                              _ptr(self.center), _ptr(self.row_ptr), _ptr(self.col), _ptr(self.w),
+                                              ctypes.byref(k), ctypes.byref(qm), _ptr(self.ws), self.wsb,
+                                              _stream(stream)), "cldiam_build_quotient")
+        kk, mm = int(k.value), int(qm.value)
+        return DeviceQuotient(kk, mm, self.center[:kk], self.row_ptr[:kk + 1], self.col[:mm], self.w[:mm])
+
+
+def cldiam_build_quotient(g: DeviceGraph, cluster, D, stream=None) -> DeviceQuotient:
+    return QuotientJob(g).run(cluster, D, stream)
+
+
+class EstimateJob:
+    def __init__(self, max_k: int, max_qm: int, device="cuda"):
+        self.lib = load_library()
+        self.wsb = self.lib.cldiam_estimate_workspace_size(max(max_k, 1), max_qm)
+        self.ws = _ws(self.wsb, device)
+
+    def run(self, q: DeviceQuotient, radius: int, stream=None):
+        need = self.lib.cldiam_estimate_workspace_size(max(q.k, 1), q.qm)
+        if need > self.wsb:
+            self.wsb = need
+            self.ws = _ws(need, q.row_ptr.device)
+        phi, approx = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.cldiam_estimate_diameter(q.k, q.qm, _ptr(q.row_ptr), _ptr(q.col), _ptr(q.w), radius,
+                                                 ctypes.byref(phi), ctypes.byref(approx), _ptr(self.ws), self.wsb,
+                                                 _stream(stream)), "cldiam_estimate_diameter")
+        return int(phi.value), int(approx.value)
+
+
+def cldiam_estimate_diameter(q: DeviceQuotient, radius: int, stream=None):
+    """(Phi(G_C), Phi(G_C) + 2 radius)."""
+    return EstimateJob(q.k, q.qm, q.row_ptr.device).run(q, radius, stream)
+
+
+# ----------------------------------------------------------------- SSSP --
+
+def default_bucket_delta(g: DeviceGraph) -> int:
+    """Bucket width used when none is given: 16 x the mean arc weight."""
+    mean = g.weight_sum // g.m if g.m else 1
+    return int(max(1, min(16 * mean, 2**31)))
+
+
+def cldiam_sssp_delta_stepping(g: DeviceGraph, source: int, bucket_delta: int = 0, stream=None):
+    """(dist int32 tensor holding uint32 bit patterns, max finite distance)."""
+    torch = _torch()
+    lib = load_library()
+    dist = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+    wsb = lib.cldiam_sssp_workspace_size(g.n, g.m)
+    ws = _ws(wsb, g.row_ptr.device)
+    mx = ctypes.c_uint64()
+    bd = bucket_delta or default_bucket_delta(g)
+    _check(lib.cldiam_sssp_delta_stepping(g.n, g.m, _ptr(g.row_ptr), _ptr(g.arcs), source, bd, _ptr(dist),
+                                          ctypes.byref(mx), _ptr(ws), wsb, _stream(stream)),
+           "cldiam_sssp_delta_stepping")
+    return dist, int(mx.value)
+
+
+# -------------------------------------------------------------- helpers --
+
+def u64(t) -> np.ndarray:
+    """Device int64 tensor holding uint64 bit patterns -> numpy uint64."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def u32(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def estimate(graph, tau: int, seed: int, delta0: int = 0, device="cuda"):
+    """Whole CL-DIAM pipeline on a host graph: ingest, decomposition,
+    quotient, estimate.  Returns a dict of host results."""
+    g = cldiam_load_csr(graph, device)
+    cluster, D, st = cldiam_decompose(g, tau, seed, delta0)
+    q = cldiam_build_quotient(g, cluster, D)
+    phi, approx = cldiam_estimate_diameter(q, st.radius)
+    return dict(cluster=cluster.cpu().numpy(), D=u64(D), stats=st, k=q.k, phi_gc=phi, phi_approx=approx)

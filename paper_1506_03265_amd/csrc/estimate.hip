@@ -1,0 +1,125 @@
+// Diameter estimate (Section 4 of arXiv:1506.03265):
+//   Phi_approx = Phi(G_C) + 2 * radius,
+// where Phi(G_C) is the largest finite shortest-path distance between two
+// nodes of the quotient graph.  G_C is small (the number of clusters), so it
+// is solved exactly: every workgroup runs single-source shortest paths from
+// one quotient node at a time (label-correcting relaxation with a
+// deduplicated queue; all distances exact at the fixpoint), keeping distances
+// and queues in LDS when they fit, in a per-workgroup workspace slice
+// otherwise.
+#include "common.h"
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kLdsMaxK = 3072;  // 20 bytes per node -> 60 KB
+
+struct ECtl {
+  unsigned long long phi;
+};
+
+__device__ void sssp_block(int32_t k, const int64_t *rp, const int32_t *col, const uint64_t *w, int32_t s,
+                           uint64_t *dist, uint32_t *stamp, int32_t *q0, int32_t *q1, uint64_t *phi) {
+  __shared__ uint32_t qn_next;
+  __shared__ unsigned long long bmax;
+  for (int32_t v = threadIdx.x; v < k; v += blockDim.x) { dist[v] = CLD_INF64; stamp[v] = 0; }
+  if (threadIdx.x == 0) { qn_next = 0; bmax = 0; }
+  __syncthreads();
+  if (threadIdx.x == 0) { dist[s] = 0; q0[0] = s; }
+  __syncthreads();
+  uint32_t qn = 1, iter = 1;
+  int32_t *qc = q0, *qx = q1;
+  while (qn > 0) {
+    for (uint32_t i = threadIdx.x; i < qn; i += blockDim.x) {
+      const int32_t u = qc[i];
+      const uint64_t du = dist[u];
+      for (int64_t a = rp[u]; a < rp[u + 1]; ++a) {
+        const int32_t v = col[a];
+        const uint64_t nd = du + w[a];
+        if (nd < dist[v]) {
+          const uint64_t old = atomicMin((unsigned long long *)&dist[v], (unsigned long long)nd);
+          if (nd < old && atomicExch(&stamp[v], iter) != iter) qx[atomicAdd(&qn_next, 1u)] = v;
+        }
+      }
+    }
+    __syncthreads();
+    qn = qn_next;
+    __syncthreads();
+    if (threadIdx.x == 0) qn_next = 0;
+    int32_t *t = qc; qc = qx; qx = t;
+    ++iter;
+    __syncthreads();
+  }
+  unsigned long long m = 0;
+  for (int32_t v = threadIdx.x; v < k; v += blockDim.x)
+    if (dist[v] != CLD_INF64 && dist[v] > m) m = dist[v];
+  atomicMax(&bmax, m);
+  __syncthreads();
+  if (threadIdx.x == 0 && bmax) atomicMax((unsigned long long *)phi, bmax);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kT) k_apsp_lds(int32_t k, const int64_t *rp, const int32_t *col,
+                                                 const uint64_t *w, uint64_t *phi) {
+  extern __shared__ uint64_t lds[];
+  uint64_t *dist = lds;
+  uint32_t *stamp = (uint32_t *)(dist + k);
+  int32_t *q0 = (int32_t *)(stamp + k);
+  int32_t *q1 = q0 + k;
+  for (int32_t s = blockIdx.x; s < k; s += gridDim.x) sssp_block(k, rp, col, w, s, dist, stamp, q0, q1, phi);
+}
+
+__global__ void __launch_bounds__(kT) k_apsp_global(int32_t k, const int64_t *rp, const int32_t *col,
+                                                    const uint64_t *w, uint64_t *phi, char *scratch) {
+  const size_t per = (size_t)k * 20;
+  char *base = scratch + per * blockIdx.x;
+  uint64_t *dist = (uint64_t *)base;
+  uint32_t *stamp = (uint32_t *)(dist + k);
+  int32_t *q0 = (int32_t *)(stamp + k);
+  int32_t *q1 = q0 + k;
+  for (int32_t s = blockIdx.x; s < k; s += gridDim.x) sssp_block(k, rp, col, w, s, dist, stamp, q0, q1, phi);
+}
+
+int grid_for(int32_t k) { return k < 1024 ? k : 1024; }
+
+}  // namespace
+
+extern "C" size_t cldiam_estimate_workspace_size(int32_t k, int64_t qm) {
+  (void)qm;
+  if (k < 1) return 0;
+  size_t s = 256;
+  if (k > kLdsMaxK) s += (size_t)k * 20 * grid_for(k) + 256;
+  return s;
+}
+
+extern "C" int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, const int32_t *d_qcol,
+                                        const uint64_t *d_qw, uint64_t radius, uint64_t *h_phi_gc,
+                                        uint64_t *h_phi_approx, void *ws, size_t ws_bytes, void *stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (k < 1 || qm < 0 || !d_qrow_ptr || (qm && (!d_qcol || !d_qw)) || !h_phi_gc || !h_phi_approx) {
+    cld::set_error("estimate_diameter: invalid arguments");
+    return CLDIAM_EINVAL;
+  }
+  cld::Arena a(ws, ws_bytes);
+  ECtl *ctl = a.take<ECtl>(1);
+  char *scratch = nullptr;
+  if (k > kLdsMaxK) scratch = a.take<char>((size_t)k * 20 * grid_for(k));
+  if (!ctl || (k > kLdsMaxK && !scratch)) {
+    cld::set_error("estimate_diameter: workspace of %zu bytes, %zu needed", ws_bytes,
+                   cldiam_estimate_workspace_size(k, qm));
+    return CLDIAM_ENOMEM;
+  }
+  CLD_HIP(hipMemsetAsync(ctl, 0, sizeof(ECtl), stream));
+  if (k <= kLdsMaxK) {
+    k_apsp_lds<<<grid_for(k), kT, (size_t)k * 20, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi);
+  } else {
+    k_apsp_global<<<grid_for(k), kT, 0, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi, scratch);
+  }
+  CLD_LAUNCH_CHECK("k_apsp");
+  ECtl h;
+  CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
+  CLD_HIP(hipStreamSynchronize(stream));
+  *h_phi_gc = h.phi;
+  *h_phi_approx = h.phi + 2 * radius;
+  return CLDIAM_OK;
+}

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point the public header
+declares; host-only queries work without a GPU."""
+import os
+import re
+
+import pytest
+
+import paper_1506_03265_amd as cd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cldiam.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cldiam_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(cd.LIB_PATH):
+        from paper_1506_03265_amd import build
+        build.build()
+    return cd.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    assert names == sorted(cd.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.cldiam_strerror(cd.CLDIAM_OK) == b"ok"
+    assert b"overflow" in lib.cldiam_strerror(cd.CLDIAM_EOVERFLOW)
+    assert b"gfx950" in lib.cldiam_version()
+
+
+def test_workspace_queries_are_monotone(lib):
+    small = lib.cldiam_decompose_workspace_size(1000, 1)
+    big = lib.cldiam_decompose_workspace_size(10**7, 1)
+    assert 0 < small < big
+    assert lib.cldiam_decompose_workspace_size(0, 1) == 0
+    assert lib.cldiam_decompose_workspace_size(1000, 256) > small
+    assert lib.cldiam_load_csr_workspace_size(100, 400) > 0
+    assert lib.cldiam_quotient_workspace_size(100, 400) > 0
+    assert lib.cldiam_estimate_workspace_size(10, 20) > 0
+    assert lib.cldiam_sssp_workspace_size(100, 400) > 0
+
+
+def test_invalid_arguments_fail_before_touching_a_device(lib):
+    # no graphs at all: rejected by host validation
+    assert lib.cldiam_decompose_batch(0, None, None, 0, None, 0, None) == cd.CLDIAM_EINVAL
+    assert b"num_graphs" in lib.cldiam_last_error()
+    # null quotient outputs
+    assert lib.cldiam_build_quotient(0, 0, None, None, None, None, None, None, None, None, None, None, None, 0,
+                                     None) == cd.CLDIAM_EINVAL
+    assert lib.cldiam_sssp_delta_stepping(10, 0, None, None, 0, 1, None, None, None, 0, None) == cd.CLDIAM_EINVAL

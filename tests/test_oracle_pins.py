@@ -278,6 +278,15 @@ def test_default_delta_is_floor_of_mean_arc_weight():
     assert oracle.decompose(g, 1, 1).delta0 == oracle.default_delta(g)
 
 
+def test_single_node_and_pair():
+    for n in (1, 2):
+        g = graphgen.csr_from_edges_np(n, [0] if n == 2 else [], [1] if n == 2 else [], [4] if n == 2 else [])
+        dec = oracle.decompose(g, 1, 1)
+        assert dec.stages == 0 and dec.num_clusters == n and dec.cluster.tolist() == list(range(n))
+        ref = brute.cluster(n, _edges(g), 1, 1)
+        _assert_same(dec, ref, f"n{n}")
+
+
 def test_overflow_is_reported():
     n = 128
     g = graphgen.csr_from_edges_np(n, range(n - 1), range(1, n), [2**31] * (n - 1))
