@@ -124,7 +124,9 @@ typedef struct {
   uint64_t radius;      /* max over nodes of D */
   uint64_t arcs_scanned;/* arcs read by relaxation (schedule dependent) */
   int32_t status;       /* per-graph status (CLDIAM_OK or an error) */
-  int32_t pad;
+  int32_t grid_blocks;  /* workgroups of the persistent launch (0 = host-driven) */
+  float kernel_ms;      /* device time of the job's control loop (HIP events) */
+  int32_t iterations;   /* control steps of the whole job */
   /* per stage s < min(stages, CLDIAM_STAGE_LOG) */
   int32_t stage_uncovered[CLDIAM_STAGE_LOG];
   int32_t stage_centers[CLDIAM_STAGE_LOG];
@@ -133,7 +135,7 @@ typedef struct {
 } cldiam_stats;
 
 /* Driver of the device-side control loop. */
-#define CLDIAM_DRIVER_AUTO 0       /* persistent kernel when the device allows it */
+#define CLDIAM_DRIVER_AUTO 0       /* the faster driver on this device (host-driven on MI355X) */
 #define CLDIAM_DRIVER_HOST 1       /* one launch per sweep, host polls */
 #define CLDIAM_DRIVER_PERSISTENT 2 /* one cooperative launch for the whole job */
 

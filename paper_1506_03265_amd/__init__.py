@@ -64,7 +64,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("stages", ctypes.c_int32), ("levels", ctypes.c_int32), ("delta0", ctypes.c_uint32),
                 ("delta_end", ctypes.c_uint32), ("stop", ctypes.c_int32), ("num_clusters", ctypes.c_int32),
                 ("singletons", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("radius", ctypes.c_uint64),
-                ("arcs_scanned", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("arcs_scanned", ctypes.c_uint64), ("status", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_float), ("iterations", ctypes.c_int32),
                 ("stage_uncovered", ctypes.c_int32 * STAGE_LOG), ("stage_centers", ctypes.c_int32 * STAGE_LOG),
                 ("stage_covered", ctypes.c_int32 * STAGE_LOG), ("stage_delta", ctypes.c_uint32 * STAGE_LOG)]
 
@@ -203,6 +204,9 @@ class Stats:
     radius: int
     arcs_scanned: int
     status: int
+    grid_blocks: int
+    kernel_ms: float
+    iterations: int
     stage_uncovered: list = field(default_factory=list)
     stage_centers: list = field(default_factory=list)
     stage_covered: list = field(default_factory=list)
@@ -212,7 +216,8 @@ class Stats:
 def _stats(s: _Stats) -> Stats:
     k = min(s.stages, STAGE_LOG)
     return Stats(s.stages, s.levels, s.delta0, s.delta_end, s.stop, s.num_clusters, s.singletons, s.sweeps,
-                 int(s.radius), int(s.arcs_scanned), s.status, list(s.stage_uncovered[:k]),
+                 int(s.radius), int(s.arcs_scanned), s.status, s.grid_blocks, float(s.kernel_ms), s.iterations,
+                 list(s.stage_uncovered[:k]),
                  list(s.stage_centers[:k]), list(s.stage_covered[:k]), list(s.stage_delta[:k]))
 
 

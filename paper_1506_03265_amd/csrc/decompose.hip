@@ -11,10 +11,10 @@
 // and all graphs advance in lock step through "sweeps": in one sweep every
 // graph contributes the items of the list its phase works on (uncovered
 // nodes, frontier, blocked nodes or newly covered nodes), the items of all
-// graphs form one index space, and every wave of the grid takes 64 of them.
-// Between sweeps one workgroup runs the per-graph control step (one thread
-// per graph), which applies Algorithm 1's decisions: coverage test, Delta
-// doubling, stage end, termination.
+// graphs form one index space, and each workgroup takes one contiguous range
+// of it.  Between sweeps one workgroup runs the per-graph control step (one
+// thread per graph), which applies Algorithm 1's decisions: coverage test,
+// Delta doubling, stage end, termination.
 //
 // Node state is one u64 key per node: (growth distance << 32) | center id,
 // ~0 when unset.  An offer (d_u + w, c_u) is applied with a 64-bit atomicMin,
@@ -42,6 +42,11 @@
 //     and after the stage it is the set of assigned nodes adjacent to the
 //     remaining uncovered nodes, i.e. the sources of the next stage.
 //
+// Pushes are staged in LDS per workgroup and written out with one global
+// reservation per list and flush; every list counter sits in its own 128-byte
+// line, so the serialisation of same-address atomics stays off the critical
+// path.
+//
 // Drivers: a persistent cooperative kernel that alternates sweep and control
 // with grid barriers (one launch per job), or host-driven launches of a sweep
 // kernel and a control kernel (the host polls a done flag).  Both run the
@@ -49,6 +54,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -85,22 +91,33 @@ struct GDesc {
   uint32_t pad;
 };
 
+// Control-owned state of one graph.
 struct GState {
-  // control-owned
   uint32_t phase, stage, delta, level_id;
   uint64_t T;
   uint32_t nU, ucur;
   uint32_t fcur, fnxt, blk;
   int32_t status;
   uint32_t levels, sweeps, centers_total, singletons;
-  // sweep counters
-  uint32_t cnt[3];
-  uint32_t cntU[2];
-  uint32_t cntC;
-  uint32_t centers;
-  uint64_t next;
-  uint64_t radius;
-  uint64_t arcs;
+};
+
+struct alignas(128) PadU32 {
+  uint32_t v;
+  uint32_t pad_[31];
+};
+struct alignas(128) PadU64 {
+  unsigned long long v;
+  uint32_t pad_[30];
+};
+
+// Counters written by sweeps, one 128-byte line each.
+struct GCount {
+  PadU32 cnt[3];   // pool lists
+  PadU32 cntU[2];  // uncovered lists
+  PadU32 cntC;     // covered list
+  PadU32 centers;  // centers drawn in this stage
+  PadU64 next;     // NEXT: smallest reach distance
+  PadU64 radius;   // max D
 };
 
 struct Ctl {
@@ -110,15 +127,16 @@ struct Ctl {
   uint32_t error;     // first error status (as positive code) or 0
   uint32_t iterations;
   uint32_t timeout;   // barrier wait gave up
-  unsigned long long arcs;  // arcs read by relaxation (diagnostic)
   unsigned long long t_start;   // wall clock at the first control step
   unsigned long long t_limit;   // ticks after which the job stops with a timeout
+  PadU64 arcs;                  // arcs read by relaxation (diagnostic)
   CldBarrier bar;
 };
 
 struct Job {
   const GDesc *desc;
   GState *st;
+  GCount *cn;
   Ctl *ctl;
   uint32_t *seg;     // G + 1 exclusive prefix of per-graph sweep items
   int32_t *log;      // G x CLDIAM_STAGE_LOG x 4
@@ -130,19 +148,23 @@ struct Job {
   int32_t *U[2];
   int32_t *C;
   int32_t G;
+  int32_t local_rounds;   // local relaxation rounds per RELAX run
 };
 
-constexpr int kThreads = 256;
-constexpr int kJobSeconds = 60;  // device-side limit of one decomposition job
+constexpr int kThreads = 1024;
+constexpr int kStageCap = 4096;   // LDS staging slots per output list
+constexpr int kLocalCap = 4096;   // LDS local-round queue slots
+constexpr int kLocalRounds = 4;   // default local relaxation rounds per RELAX run
+constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 
 // ------------------------------------------------------------- control --
 
-__device__ uint32_t items_of(const GState &s) {
+__device__ uint32_t items_of(const GState &s, const GCount &c) {
   switch (s.phase) {
-    case PH_SELECT: case PH_COMPACT: case PH_SINGLE: return s.cntU[s.ucur];
-    case PH_RELAX: return s.cnt[s.fcur];
-    case PH_NEXT: return s.cnt[s.blk];
-    case PH_ASSIGN: case PH_RMAX: return s.cntC;
+    case PH_SELECT: case PH_COMPACT: case PH_SINGLE: return c.cntU[s.ucur].v;
+    case PH_RELAX: return c.cnt[s.fcur].v;
+    case PH_NEXT: return c.cnt[s.blk].v;
+    case PH_ASSIGN: case PH_RMAX: return c.cntC.v;
     default: return 0;
   }
 }
@@ -153,7 +175,7 @@ __device__ void fail(GState &s, Ctl *ctl, int status) {
   atomicCAS(&ctl->error, 0u, (uint32_t)(-status));
 }
 
-__device__ void begin_stage(const GDesc &d, GState &s, Ctl *ctl) {
+__device__ void begin_stage(const GDesc &d, GState &s, GCount &c, Ctl *ctl) {
   if (s.nU == 0 || s.nU < d.stop || d.n < 2) {
     s.phase = PH_SINGLE;
     return;
@@ -164,8 +186,8 @@ __device__ void begin_stage(const GDesc &d, GState &s, Ctl *ctl) {
   }
   double p = d.K / (double)s.nU;
   s.T = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0);
-  s.centers = 0;
-  s.cntC = 0;
+  c.centers.v = 0;
+  c.cntC.v = 0;
   s.phase = PH_SELECT;
 }
 
@@ -173,38 +195,40 @@ __device__ void begin_stage(const GDesc &d, GState &s, Ctl *ctl) {
 __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
   const GDesc &d = job.desc[g];
   GState &s = job.st[g];
+  GCount &c = job.cn[g];
   switch (s.phase) {
     case PH_START:
       s.delta = d.delta0;
       s.stage = 0;
       s.nU = (uint32_t)d.n;
-      s.cntU[0] = (uint32_t)d.n;
+      c.cntU[0].v = (uint32_t)d.n;
       s.ucur = 0;
       s.fcur = 0; s.fnxt = 1; s.blk = 2;
-      s.cnt[0] = s.cnt[1] = s.cnt[2] = 0;
+      c.cnt[0].v = c.cnt[1].v = c.cnt[2].v = 0;
+      c.radius.v = 0;
       if ((uint64_t)s.delta > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); break; }
-      begin_stage(d, s, job.ctl);
+      begin_stage(d, s, c, job.ctl);
       break;
     case PH_SELECT:
       // frontier = sources from the previous stage + the new centers
-      s.centers_total += s.centers;
+      s.centers_total += c.centers.v;
       s.level_id = sweep_id;
       s.levels++;
       s.phase = PH_RELAX;
       break;
     case PH_RELAX:
       s.sweeps++;
-      if (s.cnt[s.fnxt] > 0) {
+      if (c.cnt[s.fnxt].v > 0) {
         uint32_t t = s.fcur; s.fcur = s.fnxt; s.fnxt = t;
-        s.cnt[s.fnxt] = 0;
+        c.cnt[s.fnxt].v = 0;
       } else {
-        s.cnt[s.fcur] = 0;
-        if (2ull * s.cntC >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
-        else { s.next = CLD_INF64; s.phase = PH_NEXT; }
+        c.cnt[s.fcur].v = 0;
+        if (2ull * c.cntC.v >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
+        else { c.next.v = CLD_INF64; s.phase = PH_NEXT; }
       }
       break;
     case PH_NEXT:
-      if (s.next == CLD_INF64) {
+      if (c.next.v == CLD_INF64) {
         s.phase = PH_ASSIGN;
       } else {
         uint64_t dl = s.delta;
@@ -212,11 +236,11 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
           if (2 * dl > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); return; }
           dl *= 2;
           s.levels++;
-        } while (dl < s.next);
+        } while (dl < c.next.v);
         s.delta = (uint32_t)dl;
         // rescan the blocked nodes at the new Delta; fresh blocked list
         uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
-        s.cnt[s.blk] = 0;
+        c.cnt[s.blk].v = 0;
         s.level_id = sweep_id;
         s.phase = PH_RELAX;
       }
@@ -224,24 +248,23 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
     case PH_ASSIGN:
       s.phase = PH_RMAX;
       break;
-    case PH_RMAX: {
-      s.cntU[s.ucur ^ 1] = 0;
+    case PH_RMAX:
+      c.cntU[s.ucur ^ 1].v = 0;
       s.phase = PH_COMPACT;
       break;
-    }
     case PH_COMPACT: {
       if (s.stage < CLDIAM_STAGE_LOG) {
         int32_t *lg = job.log + ((size_t)g * CLDIAM_STAGE_LOG + s.stage) * 4;
-        lg[0] = (int32_t)s.nU; lg[1] = (int32_t)s.centers; lg[2] = (int32_t)s.cntC; lg[3] = (int32_t)s.delta;
+        lg[0] = (int32_t)s.nU; lg[1] = (int32_t)c.centers.v; lg[2] = (int32_t)c.cntC.v; lg[3] = (int32_t)s.delta;
       }
       s.ucur ^= 1;
-      s.nU = s.cntU[s.ucur];
+      s.nU = c.cntU[s.ucur].v;
       s.stage++;
       // sources of the next stage: the blocked list of the last level
       uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
-      s.cnt[s.blk] = 0;
-      s.cnt[s.fnxt] = 0;
-      begin_stage(d, s, job.ctl);
+      c.cnt[s.blk].v = 0;
+      c.cnt[s.fnxt].v = 0;
+      begin_stage(d, s, c, job.ctl);
       break;
     }
     case PH_SINGLE:
@@ -273,7 +296,7 @@ __device__ void control_block(const Job &job) {
     if (g < job.G) {
       if (ctl->error == 0 || job.st[g].phase == PH_DONE) control_graph(job, g, sweep_id);
       if (ctl->error != 0 && job.st[g].phase != PH_DONE) job.st[g].phase = PH_DONE;
-      items = items_of(job.st[g]);
+      items = items_of(job.st[g], job.cn[g]);
       if (job.st[g].phase != PH_DONE) atomicAnd(&alldone, 0u);
     }
     scan[threadIdx.x] = items;
@@ -296,60 +319,129 @@ __device__ void control_block(const Job &job) {
     ctl->iterations++;
     ctl->done = alldone;
   }
+  __syncthreads();
 }
 
 // --------------------------------------------------------------- sweeps --
 
-__device__ __forceinline__ void push(const Job &job, int32_t *list, uint32_t *counter, int64_t off, bool pred,
-                                     int32_t v) {
-  uint32_t slot = cld_wave_reserve(pred, counter);
-  if (pred) list[off + slot] = v;
+// LDS staging of up to three output lists of one graph run.
+struct Stage {
+  int32_t buf[3][kStageCap];
+  int32_t lq[2][kLocalCap];  // local relaxation queues
+  uint32_t lq_cnt[2];
+  uint32_t cnt[3];
+  uint32_t base[3];
+  unsigned long long acc;   // min (NEXT) or max (ASSIGN) accumulator
+  uint32_t acc32;           // centers drawn (SELECT)
+  uint32_t flush;           // a list passed the flush threshold
+};
+
+struct Out {
+  int32_t *list;     // list base for this graph (offset applied)
+  uint32_t *count;   // its global counter
+};
+
+// Stage v on output list k; falls back to a direct global slot when the LDS
+// buffer is full (only possible for rows with thousands of improved arcs).
+__device__ __forceinline__ void stage_push(Stage &S, const Out *out, int k, int32_t v) {
+  const uint32_t slot = atomicAdd(&S.cnt[k], 1u);
+  if (slot < kStageCap) {
+    S.buf[k][slot] = v;
+  } else {
+    out[k].list[atomicAdd(out[k].count, 1u)] = v;
+  }
+}
+
+// Writes the staged entries out: one global reservation per list.
+__device__ void stage_flush(Stage &S, const Out *out, int nout) {
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nout) {
+    const int k = threadIdx.x;
+    const uint32_t n = S.cnt[k] < kStageCap ? S.cnt[k] : kStageCap;
+    S.base[k] = n ? atomicAdd(out[k].count, n) : 0;
+    S.cnt[k] = n;
+  }
+  __syncthreads();
+  for (int k = 0; k < nout; ++k) {
+    const uint32_t n = S.cnt[k], b = S.base[k];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[k].list[b + i] = S.buf[k][i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) S.flush = 0;
+  __syncthreads();
 }
 
 // RELAX: scan the light prefix of u's row (w <= Delta - d_u) and offer
-// (d_u + w, c_u) to every neighbour.
-__device__ uint32_t relax_item(const Job &job, const GDesc &d, GState &s, uint32_t it, int32_t u) {
-  const int64_t off = d.off;
-  const uint32_t fnxt = s.fnxt, blk = s.blk, level_id = s.level_id;
-  int32_t *const fl = job.pool[fnxt];
-  int32_t *const bl = job.pool[blk];
-  const uint64_t ku = job.key[off + u];
-  const uint32_t lim = s.delta - (uint32_t)(ku >> 32);
-  int32_t a = d.row_ptr[u];
+// (d_u + w, c_u) to every neighbour.  Outputs: 0 next frontier, 1 covered,
+// 2 blocked.  Arcs are handled four at a time so that their key loads and
+// atomics are in flight together.  Improved neighbours are also appended to
+// the workgroup's local queue `lq` (when it has room) for the local rounds.
+constexpr int kArcBatch = 4;
+
+__device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v) {
+  const uint32_t slot = atomicAdd(lq_cnt, 1u);
+  if (slot < kLocalCap) lq[slot] = v;
+}
+
+__device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
+                                               uint32_t it, uint32_t level_id, int32_t u, Stage &S,
+                                               const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+  const int32_t a0 = d.row_ptr[u];
   const int32_t a1 = d.row_ptr[u + 1];
+  const uint64_t ku = job.key[off + u];
+  const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
   uint32_t scanned = 0;
-  for (; a < a1; ++a) {
-    const uint64_t arc = d.arcs[a];
-    const uint32_t w = (uint32_t)(arc >> 32);
-    if (w > lim) { blocked = true; break; }
-    ++scanned;
-    const int64_t gv = off + (int32_t)(uint32_t)arc;
-    const uint64_t cand = ku + ((uint64_t)w << 32);
-    bool newly = false, front = false;
-    if (cand < job.key[gv]) {
-      const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
-      if (cand < old) {
-        newly = (old == CLD_INF64);
-        if (job.fstamp[gv] != it) front = atomicExch(&job.fstamp[gv], it) != it;
-      }
+  for (int32_t base = a0; base < a1 && !blocked; base += kArcBatch) {
+    uint64_t arc[kArcBatch], cur[kArcBatch];
+    bool ok[kArcBatch];
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < a1 ? d.arcs[base + j] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const bool in = base + j < a1;
+      ok[j] = in && (uint32_t)(arc[j] >> 32) <= lim;
+      if (in && !ok[j]) blocked = true;
+      scanned += ok[j];
     }
-    const int32_t v = (int32_t)(uint32_t)arc;
-    push(job, job.C, &s.cntC, off, newly, v);
-    push(job, fl, &s.cnt[fnxt], off, front, v);
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) cur[j] = ok[j] ? job.key[off + (int32_t)(uint32_t)arc[j]] : 0ull;
+    // An offer that beats the key it read is applied with atomicMin and, in
+    // the same round trip, stamps the target for the next frontier.  The
+    // stamp may be taken by an offer that then loses to a concurrent better
+    // one; the node is then still on the frontier (harmless), and an improver
+    // never finds the node missing from it.
+    bool front[kArcBatch];
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const uint64_t cand = ku + (arc[j] & 0xffffffff00000000ull);
+      ok[j] = ok[j] && cand < cur[j];
+      const int64_t gv = off + (int32_t)(uint32_t)arc[j];
+      cur[j] = ok[j] ? atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand) : 0ull;
+      front[j] = ok[j] && atomicExch(&job.fstamp[gv], it) != it;
+      ok[j] = ok[j] && cand < cur[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const int32_t v = (int32_t)(uint32_t)arc[j];
+      if (front[j]) stage_push(S, out, 0, v);
+      if (!ok[j]) continue;
+      if (cur[j] == CLD_INF64) stage_push(S, out, 1, v);
+      if (lq) lq_push(lq_cnt, lq, v);
+    }
   }
-  bool addb = false;
-  if (blocked && job.bstamp[off + u] != level_id) addb = atomicExch(&job.bstamp[off + u], level_id) != level_id;
-  push(job, bl, &s.cnt[blk], off, addb, u);
+  if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
+    stage_push(S, out, 2, u);
   return scanned;
 }
 
 // NEXT: smallest d_u + w over arcs from blocked node u to unreached nodes.
-__device__ void next_item(const Job &job, const GDesc &d, GState &s, int32_t u) {
-  const int64_t off = d.off;
+__device__ __forceinline__ uint64_t next_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
+                                              int32_t u) {
   const uint64_t ku = job.key[off + u];
   const uint32_t du = (uint32_t)(ku >> 32);
-  const uint32_t lim = s.delta - du;
+  const uint32_t lim = delta - du;
   const int32_t a0 = d.row_ptr[u];
   uint64_t best = CLD_INF64;
   for (int32_t a = d.row_ptr[u + 1] - 1; a >= a0; --a) {
@@ -361,66 +453,142 @@ __device__ void next_item(const Job &job, const GDesc &d, GState &s, int32_t u) 
       best = c < best ? c : best;
     }
   }
-  if (best != CLD_INF64) atomicMin((unsigned long long *)&s.next, (unsigned long long)best);
+  return best;
 }
 
-__device__ uint32_t process(const Job &job, int g, uint32_t idx, uint32_t it) {
+// Items [a, b) of the index space, all of graph g.
+__device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, uint32_t it, Stage &S) {
   const GDesc &d = job.desc[g];
-  GState &s = job.st[g];
+  const GState &s = job.st[g];
+  GCount &cn = job.cn[g];
   const int64_t off = d.off;
-  uint32_t scanned = 0;
-  switch (s.phase) {
-    case PH_SELECT: {
-      const int32_t v = job.U[s.ucur][off + idx];
-      const uint32_t x0 = cld_philox_word0((uint32_t)v, s.stage, 0u, 0u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-      const bool c = (uint64_t)x0 < s.T;
-      if (c) job.key[off + v] = (uint64_t)(uint32_t)v;
-      push(job, job.pool[s.fcur], &s.cnt[s.fcur], off, c, v);
-      push(job, job.C, &s.cntC, off, c, v);
-      unsigned long long m = __ballot(c);
-      if (m && cld_lane() == __ffsll((long long)m) - 1) atomicAdd(&s.centers, (uint32_t)__popcll(m));
+  const uint32_t phase = s.phase, base_idx = job.seg[g];
+  const uint32_t delta = s.delta, level_id = s.level_id, stage = s.stage, ucur = s.ucur;
+  const uint32_t fcur = s.fcur, fnxt = s.fnxt, blk = s.blk;
+  const uint64_t T = s.T;
+  Out out[3];
+  int nout = 0;
+  switch (phase) {
+    case PH_SELECT:
+      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      out[1] = {job.C + off, &cn.cntC.v};
+      nout = 2;
       break;
-    }
     case PH_RELAX:
-      scanned = relax_item(job, d, s, it, job.pool[s.fcur][off + idx]);
+      out[0] = {job.pool[fnxt] + off, &cn.cnt[fnxt].v};
+      out[1] = {job.C + off, &cn.cntC.v};
+      out[2] = {job.pool[blk] + off, &cn.cnt[blk].v};
+      nout = 3;
       break;
-    case PH_NEXT:
-      next_item(job, d, s, job.pool[s.blk][off + idx]);
+    case PH_COMPACT:
+      out[0] = {job.U[ucur ^ 1] + off, &cn.cntU[ucur ^ 1].v};
+      nout = 1;
       break;
-    case PH_ASSIGN: {
-      const int32_t v = job.C[off + idx];
-      const uint64_t k = job.key[off + v];
-      const uint32_t c = (uint32_t)k;
-      const uint64_t Dv = (k >> 32) + job.R[off + c];
-      d.cluster[v] = (int32_t)c;
-      d.D[v] = Dv;
-      if (Dv > s.radius) atomicMax((unsigned long long *)&s.radius, (unsigned long long)Dv);
-      break;
-    }
-    case PH_RMAX: {
-      const int32_t v = job.C[off + idx];
-      const uint32_t c = (uint32_t)job.key[off + v];
-      const uint64_t Dv = d.D[v];
-      uint64_t *r = &job.R[off + c];
-      if (Dv > *r) atomicMax((unsigned long long *)r, (unsigned long long)Dv);
-      job.key[off + v] = (uint64_t)c;
-      break;
-    }
-    case PH_COMPACT: {
-      const int32_t v = job.U[s.ucur][off + idx];
-      const bool keep = job.key[off + v] == CLD_INF64;
-      push(job, job.U[s.ucur ^ 1], &s.cntU[s.ucur ^ 1], off, keep, v);
-      break;
-    }
-    case PH_SINGLE: {
-      const int32_t v = job.U[s.ucur][off + idx];
-      d.cluster[v] = v;
-      d.D[v] = 0;
-      break;
-    }
     default:
       break;
   }
+  if (threadIdx.x == 0) {
+    S.acc = (phase == PH_NEXT) ? CLD_INF64 : 0ull;
+    S.acc32 = 0;
+    S.lq_cnt[0] = 0;
+    S.lq_cnt[1] = 0;
+  }
+  __syncthreads();
+  uint32_t scanned = 0;
+  for (uint32_t r = a; r < b; r += blockDim.x) {
+    const uint32_t i = r + threadIdx.x;
+    if (i < b) {
+      const uint32_t idx = i - base_idx;
+      switch (phase) {
+        case PH_SELECT: {
+          const int32_t v = job.U[ucur][off + idx];
+          const uint32_t x0 = cld_philox_word0((uint32_t)v, stage, 0u, 0u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+          if ((uint64_t)x0 < T) {
+            job.key[off + v] = (uint64_t)(uint32_t)v;
+            stage_push(S, out, 0, v);
+            stage_push(S, out, 1, v);
+            atomicAdd(&S.acc32, 1u);
+          }
+          break;
+        }
+        case PH_RELAX:
+          scanned += relax_item(job, d, off, delta, it, level_id, job.pool[fcur][off + idx], S, out, &S.lq_cnt[0],
+                                S.lq[0]);
+          break;
+        case PH_NEXT: {
+          const uint64_t best = next_item(job, d, off, delta, job.pool[blk][off + idx]);
+          if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
+          break;
+        }
+        case PH_ASSIGN: {
+          const int32_t v = job.C[off + idx];
+          const uint64_t k = job.key[off + v];
+          const uint32_t c = (uint32_t)k;
+          const uint64_t Dv = (k >> 32) + job.R[off + c];
+          d.cluster[v] = (int32_t)c;
+          d.D[v] = Dv;
+          if (Dv > S.acc) atomicMax(&S.acc, (unsigned long long)Dv);
+          break;
+        }
+        case PH_RMAX: {
+          const int32_t v = job.C[off + idx];
+          const uint32_t c = (uint32_t)job.key[off + v];
+          const uint64_t Dv = d.D[v];
+          uint64_t *rr = &job.R[off + c];
+          if (Dv > *rr) atomicMax((unsigned long long *)rr, (unsigned long long)Dv);
+          job.key[off + v] = (uint64_t)c;
+          break;
+        }
+        case PH_COMPACT: {
+          const int32_t v = job.U[ucur][off + idx];
+          if (job.key[off + v] == CLD_INF64) stage_push(S, out, 0, v);
+          break;
+        }
+        case PH_SINGLE: {
+          const int32_t v = job.U[ucur][off + idx];
+          d.cluster[v] = v;
+          d.D[v] = 0;
+          break;
+        }
+        default:
+          break;
+      }
+    }
+    if (nout) {
+      __syncthreads();
+      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      __syncthreads();
+      if (S.flush) stage_flush(S, out, nout);
+    }
+  }
+  if (phase == PH_RELAX) {
+    // Local rounds: keep relaxing the neighbours this workgroup improved.
+    // Every improved node is also on the global next frontier, so these
+    // rounds only move the fixpoint closer; dropped overflow loses nothing.
+    int q = 0;
+    for (int round = 0; round < job.local_rounds; ++round) {
+      __syncthreads();
+      const uint32_t n = S.lq_cnt[q] < kLocalCap ? S.lq_cnt[q] : kLocalCap;
+      if (n == 0) break;
+      if (threadIdx.x == 0) S.lq_cnt[q ^ 1] = 0;
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
+        scanned += relax_item(job, d, off, delta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
+      __syncthreads();
+      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      __syncthreads();
+      if (S.flush) stage_flush(S, out, nout);
+      q ^= 1;
+    }
+  }
+  if (nout) stage_flush(S, out, nout);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (phase == PH_NEXT && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
+    if (phase == PH_ASSIGN && S.acc) atomicMax(&cn.radius.v, S.acc);
+    if (phase == PH_SELECT && S.acc32) atomicAdd(&cn.centers.v, S.acc32);
+  }
+  __syncthreads();
   return scanned;
 }
 
@@ -434,44 +602,31 @@ __device__ __forceinline__ int graph_of(const Job &job, uint32_t i) {
   return lo;
 }
 
-// Logical wave id with consecutive ids on one XCD (blocks are dealt to the 8
-// XCDs round-robin), so neighbouring chunks of a list share an L2.
-__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb) {
-  if (nb % 8u) return b;
-  return (b & 7u) * (nb >> 3) + (b >> 3);
-}
-
-__device__ void sweep(const Job &job, uint32_t block, uint32_t nblocks) {
+// Each workgroup takes one contiguous range of the sweep's index space and
+// walks it graph by graph.
+__device__ void sweep(const Job &job, uint32_t block, uint32_t nblocks, Stage &S) {
   const uint32_t total = job.ctl->total;
   const uint32_t it = job.ctl->sweep_id;
-  const uint32_t waves_per_block = blockDim.x >> 6;
-  const uint32_t wave = logical_block(block, nblocks) * waves_per_block + (threadIdx.x >> 6);
-  const uint32_t nwaves = nblocks * waves_per_block;
+  const uint32_t per = (total + nblocks - 1) / nblocks;
+  const uint32_t lo = block * per;
+  const uint32_t hi = lo + per < total ? lo + per : total;
+  if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) S.flush = 0;
+  __syncthreads();
   uint32_t scanned = 0;
-  for (uint32_t chunk = wave; (uint64_t)chunk * 64 < total; chunk += nwaves) {
-    const uint32_t i = chunk * 64 + (uint32_t)cld_lane();
-    int g = i < total ? graph_of(job, i) : 0x7fffffff;
-    for (;;) {
-      int gmin = g;
-      for (int o = 32; o >= 1; o >>= 1) {
-        int x = __shfl_xor(gmin, o);
-        gmin = x < gmin ? x : gmin;
-      }
-      gmin = __builtin_amdgcn_readfirstlane(gmin);
-      if (gmin == 0x7fffffff) break;
-      if (g == gmin) {
-        scanned += process(job, gmin, i - job.seg[gmin], it);
-        g = 0x7fffffff;
-      }
-    }
+  for (uint32_t i = lo; i < hi;) {
+    const int g = graph_of(job, i);
+    const uint32_t end = job.seg[g + 1] < hi ? job.seg[g + 1] : hi;
+    scanned += process_run(job, g, i, end, it, S);
+    i = end;
   }
   for (int o = 32; o >= 1; o >>= 1) scanned += __shfl_xor(scanned, o);
-  if (cld_lane() == 0 && scanned) atomicAdd(&job.ctl->arcs, (unsigned long long)scanned);
+  if (cld_lane() == 0 && scanned) atomicAdd(&job.ctl->arcs.v, (unsigned long long)scanned);
 }
 
 // ---------------------------------------------------------------- kernels --
 
-__global__ void __launch_bounds__(kThreads) k_init(Job job, int64_t total_n) {
+__global__ void __launch_bounds__(256) k_init(Job job, int64_t total_n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += stride) {
     job.key[i] = CLD_INF64;
@@ -490,17 +645,19 @@ __global__ void __launch_bounds__(kThreads) k_init(Job job, int64_t total_n) {
 __global__ void __launch_bounds__(kThreads) k_control(Job job) { control_block(job); }
 
 __global__ void __launch_bounds__(kThreads) k_sweep(Job job) {
+  __shared__ Stage S;
   if (job.ctl->done) return;
-  sweep(job, blockIdx.x, gridDim.x);
+  sweep(job, blockIdx.x, gridDim.x, S);
 }
 
 __global__ void __launch_bounds__(kThreads) k_persistent(Job job) {
+  __shared__ Stage S;
   const uint32_t nb = gridDim.x;
   for (;;) {
     if (blockIdx.x == 0) control_block(job);
     if (!cld_grid_barrier(&job.ctl->bar, &job.ctl->timeout, nb)) return;
     if (job.ctl->done || job.ctl->timeout) return;
-    sweep(job, blockIdx.x, nb);
+    sweep(job, blockIdx.x, nb, S);
     if (!cld_grid_barrier(&job.ctl->bar, &job.ctl->timeout, nb)) return;
   }
 }
@@ -510,6 +667,7 @@ __global__ void __launch_bounds__(kThreads) k_persistent(Job job) {
 struct Layout {
   GDesc *desc;
   GState *st;
+  GCount *cn;
   Ctl *ctl;
   uint32_t *seg;
   int32_t *log;
@@ -522,6 +680,7 @@ template <class A>
 bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto p_desc = a.template take<GDesc>(G);
   auto p_st = a.template take<GState>(G);
+  auto p_cn = a.template take<GCount>(G);
   auto p_ctl = a.template take<Ctl>(1);
   auto p_seg = a.template take<uint32_t>((size_t)G + 1);
   auto p_log = a.template take<int32_t>((size_t)G * CLDIAM_STAGE_LOG * 4);
@@ -536,7 +695,7 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto u1 = a.template take<int32_t>(N);
   auto c = a.template take<int32_t>(N);
   if (L) {
-    *L = Layout{(GDesc *)p_desc, (GState *)p_st, (Ctl *)p_ctl, (uint32_t *)p_seg, (int32_t *)p_log,
+    *L = Layout{(GDesc *)p_desc, (GState *)p_st, (GCount *)p_cn, (Ctl *)p_ctl, (uint32_t *)p_seg, (int32_t *)p_log,
                 (uint64_t *)p_key, (uint64_t *)p_R, (uint32_t *)p_fs, (uint32_t *)p_bs,
                 {(int32_t *)p0, (int32_t *)p1, (int32_t *)p2}, {(int32_t *)u0, (int32_t *)u1}, (int32_t *)c};
     return p_desc && c;
@@ -566,6 +725,32 @@ Ctl *host_ctl() {
     t_host_ctl = (Ctl *)p;
   }
   return t_host_ctl;
+}
+
+// Workgroups of the sweep grid: one per CU by default; CLDIAM_GRID_BLOCKS
+// overrides (bounded by the co-resident maximum for the persistent kernel).
+int grid_blocks(int driver, int *blocks) {
+  int coop_blocks = 0;
+  int rc = cld::cooperative_blocks((const void *)k_persistent, kThreads, 1, &coop_blocks);
+  if (rc) return rc;
+  int dev = 0, cus = 0;
+  CLD_HIP(hipGetDevice(&dev));
+  CLD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int want = cus;
+  if (const char *e = getenv("CLDIAM_GRID_BLOCKS")) {
+    int x = atoi(e);
+    if (x > 0) want = x;
+  }
+  if (driver == CLDIAM_DRIVER_HOST) {
+    *blocks = want;
+    return CLDIAM_OK;
+  }
+  if (coop_blocks == 0) {
+    *blocks = 0;
+    return CLDIAM_OK;
+  }
+  *blocks = want < coop_blocks ? want : coop_blocks;
+  return CLDIAM_OK;
 }
 
 }  // namespace
@@ -613,6 +798,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     d.delta0 = (uint32_t)d0;
     N += x.n;
   }
+  if (N >= ((int64_t)1 << 31)) { cld::set_error("decompose: more than 2^31 nodes in one job"); return CLDIAM_EINVAL; }
   Layout L;
   PtrArena pa(ws, ws_bytes);
   if (!carve(pa, N, G, &L) || pa.a.used > ws_bytes) {
@@ -620,13 +806,16 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     return CLDIAM_ENOMEM;
   }
   Job job;
-  job.desc = L.desc; job.st = L.st; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log; job.key = L.key;
-  job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
+  job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = G;
+  job.local_rounds = kLocalRounds;
+  if (const char *e = getenv("CLDIAM_LOCAL_ROUNDS")) job.local_rounds = atoi(e) < 0 ? 0 : atoi(e);
 
   CLD_HIP(hipMemcpyAsync(L.desc, desc.data(), sizeof(GDesc) * G, hipMemcpyHostToDevice, stream));
   CLD_HIP(hipMemsetAsync(L.st, 0, sizeof(GState) * G, stream));
+  CLD_HIP(hipMemsetAsync(L.cn, 0, sizeof(GCount) * G, stream));
   CLD_HIP(hipMemsetAsync(L.ctl, 0, sizeof(Ctl), stream));
   {
     int dev = 0, khz = 0;
@@ -637,52 +826,70 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     CLD_HIP(hipMemcpyAsync(&L.ctl->t_limit, &limit, sizeof limit, hipMemcpyHostToDevice, stream));
   }
   CLD_HIP(hipMemsetAsync(L.log, 0, sizeof(int32_t) * G * CLDIAM_STAGE_LOG * 4, stream));
-  k_init<<<cld::blocks_for(N, kThreads, 8192), kThreads, 0, stream>>>(job, N);
+  k_init<<<cld::blocks_for(N, 256, 8192), 256, 0, stream>>>(job, N);
   CLD_LAUNCH_CHECK("k_init");
 
   int blocks = 0;
-  if (driver != CLDIAM_DRIVER_HOST) {
-    int rc = cld::cooperative_blocks((const void *)k_persistent, kThreads, 4, &blocks);
+  {
+    int rc = grid_blocks(driver == CLDIAM_DRIVER_PERSISTENT ? driver : CLDIAM_DRIVER_HOST, &blocks);
     if (rc) return rc;
     if (blocks == 0 && driver == CLDIAM_DRIVER_PERSISTENT) {
       cld::set_error("decompose: device has no cooperative launch");
       return CLDIAM_EINVAL;
     }
   }
+  const bool persistent = driver == CLDIAM_DRIVER_PERSISTENT && blocks > 0;
+  if (!persistent && blocks == 0) blocks = 256;
   Ctl *hc = host_ctl();
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
-  if (blocks > 0) {
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  CLD_HIP(hipEventCreate(&ev0));
+  CLD_HIP(hipEventCreate(&ev1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); }
+  } evg{ev0, ev1};
+  CLD_HIP(hipEventRecord(ev0, stream));
+  if (persistent) {
     void *args[] = {&job};
     CLD_HIP(hipLaunchCooperativeKernel((const void *)k_persistent, dim3(blocks), dim3(kThreads), args, 0, stream));
+    CLD_HIP(hipEventRecord(ev1, stream));
     CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     CLD_HIP(hipStreamSynchronize(stream));
     if (hc->timeout) { cld::set_error("decompose: grid barrier timed out"); return CLDIAM_ETIMEOUT; }
     if (!hc->done && !hc->error) { cld::set_error("decompose: persistent kernel ended early"); return CLDIAM_EHIP; }
   } else {
-    const int sweep_blocks = 2048;
     int batch = 4;
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
       for (int i = 0; i < batch; ++i) {
         k_control<<<1, kThreads, 0, stream>>>(job);
-        k_sweep<<<sweep_blocks, kThreads, 0, stream>>>(job);
+        k_sweep<<<blocks, kThreads, 0, stream>>>(job);
       }
       CLD_LAUNCH_CHECK("k_sweep");
       CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
       CLD_HIP(hipStreamSynchronize(stream));
-      if (hc->done) break;
+      if (hc->done) {
+        CLD_HIP(hipEventRecord(ev1, stream));
+        break;
+      }
       if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(kJobSeconds + 30)) {
         cld::set_error("decompose: host-driven job exceeded its time limit");
         return CLDIAM_ETIMEOUT;
       }
       if (batch < 64) batch *= 2;
     }
+    blocks = 0;
   }
   std::vector<GState> st(G);
+  std::vector<GCount> cn(G);
   std::vector<int32_t> lg((size_t)G * CLDIAM_STAGE_LOG * 4);
   CLD_HIP(hipMemcpyAsync(st.data(), L.st, sizeof(GState) * G, hipMemcpyDeviceToHost, stream));
+  CLD_HIP(hipMemcpyAsync(cn.data(), L.cn, sizeof(GCount) * G, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipMemcpyAsync(lg.data(), L.log, sizeof(int32_t) * lg.size(), hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
+  float kernel_ms = 0.f;
+  CLD_HIP(hipEventElapsedTime(&kernel_ms, ev0, ev1));
   int rc = CLDIAM_OK;
   for (int g = 0; g < G; ++g) {
     if (st[g].status != CLDIAM_OK && rc == CLDIAM_OK) {
@@ -700,9 +907,12 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     o.num_clusters = (int32_t)(st[g].centers_total + st[g].singletons);
     o.singletons = (int32_t)st[g].singletons;
     o.sweeps = (int32_t)st[g].sweeps;
-    o.radius = st[g].radius;
-    o.arcs_scanned = (G == 1) ? hc->arcs : 0;
+    o.radius = cn[g].radius.v;
+    o.arcs_scanned = (G == 1) ? hc->arcs.v : 0;
     o.status = st[g].status;
+    o.grid_blocks = blocks;
+    o.kernel_ms = kernel_ms;
+    o.iterations = (int32_t)hc->iterations;
     for (int s = 0; s < CLDIAM_STAGE_LOG && s < o.stages; ++s) {
       const int32_t *l = &lg[((size_t)g * CLDIAM_STAGE_LOG + s) * 4];
       o.stage_uncovered[s] = l[0];

@@ -43,31 +43,39 @@ __global__ void k_center_list(const int32_t *cluster, int32_t n, const uint32_t 
     if (cluster[v] == (int32_t)v) qcenter[dense[v]] = (int32_t)v;
 }
 
-// One wave per row; every inter-cluster arc appends (key, weight).
+// One thread per row; every inter-cluster arc appends (key, weight) through
+// a wave-aggregated reservation.
 __global__ void __launch_bounds__(kT) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n,
                                              const int32_t *cluster, const uint64_t *D, const uint32_t *dense,
                                              int kb, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t u = wave; u < n; u += nwaves) {
-    const int32_t a0 = rp[u], a1 = rp[u + 1];
-    const int32_t cu = cluster[u];
-    const uint64_t du = D[u];
-    const uint64_t a = dense[cu];
-    for (int32_t base = a0; base < a1; base += 64) {
-      const int32_t i = base + lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // whole waves iterate together so that the reservation sees every lane
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t u = base + threadIdx.x;
+    int32_t a = 0, a1 = 0, cu = -1;
+    uint64_t du = 0, ka = 0;
+    if (u < n) {
+      a = rp[u];
+      a1 = rp[u + 1];
+      cu = cluster[u];
+      du = D[u];
+      ka = (uint64_t)dense[cu] << kb;
+    }
+    for (;;) {
+      const bool live = a < a1;
+      if (!__any(live)) break;
       bool emit = false;
       uint64_t key = 0, val = 0;
-      if (i < a1) {
-        const uint64_t arc = arcs[i];
+      if (live) {
+        const uint64_t arc = arcs[a];
         const int32_t v = (int32_t)(uint32_t)arc;
         const int32_t cv = cluster[v];
         if (cv != cu) {
           emit = true;
-          key = (a << kb) | (uint64_t)dense[cv];
+          key = ka | (uint64_t)dense[cv];
           val = (arc >> 32) + du + D[v];
         }
+        ++a;
       }
       const uint32_t slot = cld_wave_reserve(emit, &ctl->pairs);
       if (emit) { keys[slot] = key; vals[slot] = val; }
@@ -183,7 +191,7 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   const int32_t k = (int32_t)h.k;
   const int kb = bits_for(k > 0 ? (uint32_t)(k - 1) : 0u);
   if (m > 0) {
-    k_emit<<<cld::blocks_for((int64_t)n * 64, kT, 16384), kT, 0, stream>>>(d_row_ptr, d_arcs, n, d_cluster, d_D,
+    k_emit<<<cld::blocks_for(n, kT, 16384), kT, 0, stream>>>(d_row_ptr, d_arcs, n, d_cluster, d_D,
                                                                           dense, kb, keys, vals, ctl);
     CLD_LAUNCH_CHECK("k_emit");
   }

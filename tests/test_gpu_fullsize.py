@@ -1,0 +1,70 @@
+"""Full-size parity on the benchmark workload (road-like 4096x4096 mesh,
+16.8M nodes, 64.1M arcs, tau = 4, seed 1), in the launch configuration the
+benchmark times.  Expected values were written by the oracle
+(tests/golden/make_workload_counts.py): per-node outputs are compared through
+SHA-256 digests of the oracle's arrays, plus stage counts, the quotient size
+and the estimate."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import paper_1506_03265_amd as cd
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def road():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    counts = json.load(open(os.path.join(HERE, "golden", "road4096_counts.json")))
+    print("[fullsize] generating road4096", file=sys.stderr, flush=True)
+    g = graphgen.road_like(4096, 1)
+    assert (g.n, g.m) == (counts["n"], counts["m_arcs"])
+    return g, counts, cd.cldiam_load_csr(g)
+
+
+@pytest.mark.parametrize("driver", [cd.DRIVER_AUTO, cd.DRIVER_HOST], ids=["auto", "host"])
+def test_road4096_decompose_quotient_estimate(road, driver):
+    g, counts, dg = road
+    print(f"[fullsize] decompose driver={driver}", file=sys.stderr, flush=True)
+    cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"], driver=driver)
+    assert (st.stages, st.levels, st.delta0, st.delta_end) == \
+        (counts["stages"], counts["levels"], counts["delta0"], counts["delta_end"])
+    assert (st.num_clusters, st.singletons, st.radius) == \
+        (counts["num_clusters"], counts["singletons"], counts["radius"])
+    assert st.stage_uncovered == counts["stage_uncovered"]
+    assert st.stage_centers == counts["stage_centers"]
+    assert st.stage_covered == counts["stage_covered"]
+    assert st.stage_delta == counts["stage_delta"]
+    assert _digest(cluster.cpu().numpy()) == counts["cluster_sha256"]
+    assert _digest(cd.u64(D)) == counts["D_sha256"]
+    q = cd.cldiam_build_quotient(dg, cluster, D)
+    assert q.k == counts["quotient_k"] and q.qm == 2 * counts["quotient_edges"]
+    phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
+    assert (phi, approx) == (counts["phi_gc"], counts["phi_approx"])
+
+
+def test_road4096_invariants_on_samples(road):
+    """Properties that hold at any size, on sampled clusters: a partition
+    whose centers are their own cluster, and D bounded by the stage radii."""
+    g, counts, dg = road
+    cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"])
+    c = cluster.cpu().numpy()
+    d = cd.u64(D)
+    centers = np.unique(c)
+    assert len(centers) == st.num_clusters
+    assert np.all(c[centers] == centers)
+    assert np.all(d[centers] == 0)
+    assert int(d.max()) == st.radius <= sum(st.stage_delta)

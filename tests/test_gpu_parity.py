@@ -178,8 +178,8 @@ def test_decompose_medium(name, maker, tau, driver):
 @pytest.mark.parametrize("name,maker,tau", [("grid_small", graphgen.grid_small, 1),
                                             ("road256", lambda: graphgen.road_like(256, 2), 1),
                                             ("rmat12", lambda: graphgen.rmat(12, seed=3), 1),
-                                            ("er", lambda: TINY[3][1], 1), ("twocomp", lambda: TINY[-5][1], 1),
-                                            ("noedges", lambda: TINY[-3][1], 1), ("single", lambda: TINY[-2][1], 1)],
+                                            ("er3", lambda: _GRAPHS["er3"], 1), ("twocomp", lambda: _GRAPHS["twocomp"], 1),
+                                            ("noedges", lambda: _GRAPHS["noedges"], 1), ("single", lambda: _GRAPHS["single"], 1)],
                          ids=lambda x: x if isinstance(x, str) else "")
 def test_quotient_and_estimate(name, maker, tau):
     g = maker()
@@ -220,7 +220,7 @@ def test_estimate_global_memory_path():
                                            ("road512", lambda: graphgen.road_like(512, 3), 0),
                                            ("rmat13", lambda: graphgen.rmat(13, seed=2), 0),
                                            ("rmat13_big", lambda: graphgen.rmat(13, seed=2), 2**22),
-                                           ("twocomp", lambda: TINY[-5][1], 0)],
+                                           ("twocomp", lambda: _GRAPHS["twocomp"], 0), ("star", lambda: _GRAPHS["star"], 0)],
                          ids=lambda x: x if isinstance(x, str) else "")
 def test_sssp_equals_dijkstra(name, maker, bd):
     g = maker()
@@ -238,7 +238,7 @@ def test_sssp_equals_dijkstra(name, maker, bd):
 @pytest.mark.parametrize("driver", DRIVERS, ids=DRIVER_IDS)
 def test_batch_equals_single_and_oracle(driver):
     graphs = [graphgen.rgg(n, i, 1) for i, n in enumerate([1000, 3000, 500, 20000, 1200, 7000])]
-    graphs += [TINY[-3][1], TINY[0][1], TINY[-2][1]]
+    graphs += [_GRAPHS["noedges"], _GRAPHS["grid_small"], _GRAPHS["single"]]
     params = [(1 + (i % 2), 100 + i, 0) for i in range(len(graphs))]
     _say(f"[parity] batch of {len(graphs)} driver={driver}")
     dgs = [cd.cldiam_load_csr(g) for g in graphs]
