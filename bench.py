@@ -1,23 +1,32 @@
-"""Benchmark of the CL-DIAM hot path on one MI355X.
+"""Benchmarks of the CL-DIAM hot path on one MI355X.
 
-A step is one pass of the whole path over the workload, inputs resident in
-HBM: decomposition (CLUSTER, Algorithm 1), weighted quotient graph and the
+Default (``--workload road4096``): the line the contract asks for.  A step is
+one pass of the whole path over the workload, inputs resident in HBM:
+decomposition (CLUSTER, Algorithm 1), weighted quotient graph and the
 diameter estimate (Section 4).  Ingest (validation + weight-sorted packing of
-the CSR) runs once before the clock and is reported separately.
-
-Workload: the road-like 4096x4096 mesh (16.8M nodes, 64.1M arcs) with tau = 4,
-seed 1, initial Delta = mean arc weight.  Throughput is edges per second
-(undirected input edges / step time), in GTEPS.
+the CSR) runs once before the clock and is reported separately.  Workload:
+the road-like 4096x4096 mesh (16.8M nodes, 64.1M arcs), tau = 4, seed 1,
+initial Delta = mean arc weight.  Throughput is undirected input edges per
+second of step time, in GTEPS.
 
 The roofline object covers the dominant kernel, the decomposition's sweep
 kernel: algorithmic bytes of one decomposition (work counts of the sequential
 oracle run, stored by tests/golden/make_workload_counts.py) divided by the
 device time of the decomposition's launch loop (all its sweep and control
 launches), measured by the library with HIP events on the caller's stream,
-against the 8 TB/s HBM peak.  The CPU baseline times the oracle on the host on the same
-workload (single thread).
+against the 8 TB/s HBM peak.  The CPU baseline times the oracle on the host on
+the same workload (single thread).
 
-Prints one JSON line.  Only one GPU is supported.
+Other workloads (each prints its own JSON line):
+  --workload rmat24   the same step on R-MAT scale 24 (social-like graph)
+  --workload rgg256   256 random geometric graphs (sizes log-uniform in
+                      [1e3, 1e6]) decomposed in one device job, against one
+                      job per graph, with the schedule picked by the tuner
+  --workload serve    a Poisson request stream (meshes and R-MAT graphs)
+                      served with continuous batching, against sequential
+                      plain runs: p50/p99 latency and requests/s
+
+Only one GPU is supported.
 """
 import argparse
 import json
@@ -29,34 +38,22 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "decomposition GTEPS + % HBM roofline; p50/p99 latency served vs plain, bit-exact"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--driver", type=int, default=0, help="0 auto, 1 host-driven, 2 persistent")
-    ap.add_argument("--decompose-only", action="store_true", help="time only the decomposition (for profiles)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md for how it "
-              "would shard)", file=sys.stderr)
-        sys.exit(2)
-
+def step_bench(args, name):
     import torch
 
     import graphgen
     import paper_1506_03265_amd as cd
 
-    counts = json.load(open(os.path.join(HERE, "tests", "golden", "road4096_counts.json")))
-    log("[bench] generating road-like 4096x4096 workload")
-    g = graphgen.road_like(4096, 1)
+    counts = json.load(open(os.path.join(HERE, "tests", "golden", f"{name}_counts.json")))
+    log(f"[bench] generating {name}")
+    g = graphgen.road_like(4096, 1) if name == "road4096" else graphgen.rmat(24, seed=1)
     assert g.n == counts["n"] and g.m == counts["m_arcs"], "workload differs from the stored counts"
     torch.cuda.init()
     dev = torch.device("cuda", 0)
@@ -68,7 +65,8 @@ def main():
     ingest_ms = (time.perf_counter() - t0) * 1e3
     log(f"[bench] ingest {ingest_ms:.1f} ms (H2D + validation + packing)")
 
-    job = cd.DecomposeJob([dg], [(counts["tau"], counts["seed"], 0)], driver=args.driver)
+    job = cd.DecomposeJob([dg], [(counts["tau"], counts["seed"], 0)], driver=args.driver,
+                          local_rounds=args.local_rounds, grid_blocks=args.grid_blocks)
     qjob = cd.QuotientJob(dg)
     ejob = cd.EstimateJob(1, 1, dev)   # grows to the quotient's size on first use
 
@@ -128,8 +126,8 @@ def main():
                "sample": f"the full workload once (decompose + quotient + estimate, {tc:.1f} s single-threaded, "
                          f"host {os.cpu_count()} cpus visible)"}
 
-    out = {
-        "metric": "decomposition GTEPS + % HBM roofline; p50/p99 latency served vs plain, bit-exact",
+    return {
+        "metric": METRIC,
         "value": round(value, 6),
         "unit": "GTEPS",
         "n_gpus": 1,
@@ -149,7 +147,8 @@ def main():
                    "quotient_ms": round(quot_ms, 3), "estimate_ms": round(est_ms, 3),
                    "decompose_gteps": round(edges / (dec_ms / 1e3) / 1e9, 4),
                    "sweeps": st.sweeps, "iterations": st.iterations, "grid_blocks": st.grid_blocks,
-                   "arcs_relaxed": st.arcs_scanned, "driver": "host-driven" if st.grid_blocks == 0 else "persistent"},
+                   "arcs_relaxed": st.arcs_scanned,
+                   "driver": "host-driven" if st.grid_blocks == 0 else "persistent"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                      "kernel": ("k_sweep+k_control launch loop" if st.grid_blocks == 0 else "k_persistent")
@@ -157,6 +156,145 @@ def main():
                      "algorithmic_bytes": counts["bytes_decompose"]},
         "cpu_baseline": cpu,
     }
+
+
+def batched_bench(args):
+    import torch
+
+    import graphgen
+    import paper_1506_03265_amd as cd
+    from paper_1506_03265_amd import tune
+
+    count = args.graphs
+    log(f"[bench] generating {count} random geometric graphs")
+    graphs = graphgen.rgg_batch(count, seed=1)
+    seeds = [(g_i << 32) | 1 for g_i in range(count)]
+    params = [(1, s, 0) for s in seeds]
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    n_tot = sum(g.n for g in graphs)
+    m_tot = sum(g.m for g in graphs)
+    log(f"[bench] batch: {count} graphs, {n_tot} nodes, {m_tot} arcs")
+    best = tune.tune_batch(dgs, params)
+    log(f"[bench] tuner picked {best}")
+    batch = cd.DecomposeJob(dgs, params, **best)
+    singles = [cd.DecomposeJob([dg], [p], **best) for dg, p in zip(dgs, params)]
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats = batch.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    for j in singles:
+        j.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for j in singles:
+            j.run()
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / args.steps
+    same = all(bool((b == s.cluster[0]).all()) and bool((bd == s.D[0]).all())
+               for b, bd, s in zip(batch.cluster, batch.D, singles))
+    edges = m_tot // 2
+    return {
+        "metric": "batched decomposition throughput (one device job vs one job per graph)",
+        "value": round(edges / t_batch / 1e9, 6), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{count} random geometric graphs, sizes log-uniform in [1e3, 1e6], average "
+                               "degree 8, w = round(1e4*len)+1, largest components, tau=1, seed_g=(g<<32)|1",
+                   "graphs": count, "nodes": n_tot, "arcs": m_tot, "tuning": best,
+                   "batched_ms": round(t_batch * 1e3, 3), "one_job_per_graph_ms": round(t_single * 1e3, 3),
+                   "speedup": round(t_single / t_batch, 3), "graphs_per_s": round(count / t_batch, 1),
+                   "batched_equals_single": same,
+                   "sweeps": max(s.sweeps for s in stats), "iterations": stats[0].iterations},
+    }
+
+
+def serve_bench(args):
+    import graphgen
+    import paper_1506_03265_amd as cd
+    from paper_1506_03265_amd import serve
+
+    reqs_in = graphgen.serving_mix(args.requests, rate=args.rate, seed=1)
+
+    # meshes are quantised to sides that are multiples of 256 so that the pool
+    # of resident graphs stays small; R-MAT scales are 12..22
+    def key(r):
+        return f"grid{max(256, (r.size // 256) * 256)}" if r.kind == "grid" else f"rmat{r.size}"
+
+    keys = sorted({key(r) for r in reqs_in})
+    log(f"[bench] generating {len(keys)} resident graphs for {len(reqs_in)} requests")
+    pool = {}
+    sizes = {}
+    for k in keys:
+        if k.startswith("grid"):
+            s = int(k[4:])
+            g = graphgen.grid(s, s, 10000, s)
+        else:
+            g = graphgen.rmat(int(k[4:]), seed=int(k[4:]))
+        pool[k] = cd.cldiam_load_csr(g)
+        sizes[k] = (g.n, g.m)
+    reqs = [serve.Request(r.rid, r.arrival_s, key(r), 1, r.rid) for r in reqs_in]
+    # warm up every graph once
+    serve.serve([serve.Request(i, 0.0, k, 1, 0) for i, k in enumerate(keys)], pool, workers=1)
+    log("[bench] served run")
+    res_s, wall_s = serve.serve(reqs, pool, workers=args.workers, hbm_budget_bytes=200 << 30)
+    log("[bench] plain sequential run")
+    res_p, wall_p = serve.serve(reqs, pool, workers=1, hbm_budget_bytes=200 << 30)
+    same = all((a.num_clusters, a.radius, a.phi_approx) == (b.num_clusters, b.radius, b.phi_approx)
+               for a, b in zip(res_s, res_p))
+    lat_s = [r.latency_s * 1e3 for r in res_s]
+    lat_p = [r.latency_s * 1e3 for r in res_p]
+    edges = sum(sizes[r.graph][1] // 2 for r in reqs)
+    return {
+        "metric": "served decompose+estimate: p50/p99 latency and requests/s, served vs plain",
+        "value": round(len(reqs) / wall_s, 3), "unit": "req/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": len(keys), "ms_per_step": round(wall_s / len(reqs) * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} Poisson requests at {args.rate}/s: half meshes (side 256-2048, "
+                               "w in [1,1e4]), half R-MAT scale 12-22 (w in [1,2^20]), tau=1, seed=request id",
+                   "resident_graphs": len(keys), "workers": args.workers, "hbm_budget_gb": 200,
+                   "served": {"p50_ms": round(serve.percentile(lat_s, 50), 3),
+                              "p99_ms": round(serve.percentile(lat_s, 99), 3),
+                              "req_per_s": round(len(reqs) / wall_s, 3), "wall_s": round(wall_s, 3),
+                              "gteps": round(edges / wall_s / 1e9, 4)},
+                   "plain": {"p50_ms": round(serve.percentile(lat_p, 50), 3),
+                             "p99_ms": round(serve.percentile(lat_p, 99), 3),
+                             "req_per_s": round(len(reqs) / wall_p, 3), "wall_s": round(wall_p, 3),
+                             "gteps": round(edges / wall_p / 1e9, 4)},
+                   "served_equals_plain": same},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="road4096", choices=["road4096", "rmat24", "rgg256", "serve"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--driver", type=int, default=0, help="0 auto, 1 host-driven, 2 persistent")
+    ap.add_argument("--local-rounds", type=int, default=-1)
+    ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--decompose-only", action="store_true", help="time only the decomposition (for profiles)")
+    ap.add_argument("--graphs", type=int, default=256, help="rgg256: number of graphs")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent requests")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (DESIGN.md describes how it "
+              "would shard)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("road4096", "rmat24"):
+        out = step_bench(args, args.workload)
+    elif args.workload == "rgg256":
+        out = batched_bench(args)
+    else:
+        out = serve_bench(args)
     print(json.dumps(out), flush=True)
 
 

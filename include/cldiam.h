@@ -139,6 +139,13 @@ typedef struct {
 #define CLDIAM_DRIVER_HOST 1       /* one launch per sweep, host polls */
 #define CLDIAM_DRIVER_PERSISTENT 2 /* one cooperative launch for the whole job */
 
+/* Schedule knobs of a decomposition job.  They change only how the work is
+ * scheduled on the device, never the results. */
+typedef struct {
+  int32_t local_rounds; /* workgroup-local relaxation rounds per sweep; < 0 = default (4) */
+  int32_t grid_blocks;  /* workgroups per sweep; 0 = one per compute unit */
+} cldiam_tuning;
+
 /* One graph description of a batch (graph operand in DEVICE memory). */
 typedef struct {
   int32_t n;
@@ -158,14 +165,14 @@ size_t cldiam_decompose_workspace_size(int64_t total_n, int32_t num_graphs);
 /* Decomposes num_graphs independent graphs in one device job; per-graph
  * results equal those of separate single-graph calls.  h_stats (host,
  * num_graphs entries, may be NULL) receives per-graph statistics.
- * driver: one of CLDIAM_DRIVER_*.  A failure of one graph is reported in its
+ * driver: one of CLDIAM_DRIVER_*; tuning may be NULL (defaults).  A failure of one graph is reported in its
  * stats status and as the return value (the first failing graph's status). */
 int cldiam_decompose_batch(int32_t num_graphs, const cldiam_graph *h_graphs, cldiam_stats *h_stats, int driver,
-                           void *ws, size_t ws_bytes, void *stream);
+                           const cldiam_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
 
 /* Single-graph convenience form of cldiam_decompose_batch. */
-int cldiam_decompose(const cldiam_graph *h_graph, cldiam_stats *h_stats, int driver, void *ws, size_t ws_bytes,
-                     void *stream);
+int cldiam_decompose(const cldiam_graph *h_graph, cldiam_stats *h_stats, int driver, const cldiam_tuning *tuning,
+                     void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------- quotient graph ---
  * Weighted quotient graph G_C of Section 4: one node per cluster, numbered by

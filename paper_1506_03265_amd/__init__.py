@@ -60,6 +60,10 @@ class _Graph(ctypes.Structure):
                 ("params", _Params), ("d_cluster", ctypes.c_void_p), ("d_D", ctypes.c_void_p)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("local_rounds", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("stages", ctypes.c_int32), ("levels", ctypes.c_int32), ("delta0", ctypes.c_uint32),
                 ("delta_end", ctypes.c_uint32), ("stop", ctypes.c_int32), ("num_clusters", ctypes.c_int32),
@@ -90,8 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.cldiam_load_csr_workspace_size.argtypes, lib.cldiam_load_csr_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_load_csr.argtypes = [P(_Csr), V, P(U64), V, SZ, V]
     lib.cldiam_decompose_workspace_size.argtypes, lib.cldiam_decompose_workspace_size.restype = [I64, I32], SZ
-    lib.cldiam_decompose_batch.argtypes = [I32, P(_Graph), P(_Stats), ctypes.c_int, V, SZ, V]
-    lib.cldiam_decompose.argtypes = [P(_Graph), P(_Stats), ctypes.c_int, V, SZ, V]
+    lib.cldiam_decompose_batch.argtypes = [I32, P(_Graph), P(_Stats), ctypes.c_int, P(_Tuning), V, SZ, V]
+    lib.cldiam_decompose.argtypes = [P(_Graph), P(_Stats), ctypes.c_int, P(_Tuning), V, SZ, V]
     lib.cldiam_quotient_workspace_size.argtypes, lib.cldiam_quotient_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_build_quotient.argtypes = [I32, I64, V, V, V, V, V, V, V, V, P(I32), P(I64), V, SZ, V]
     lib.cldiam_estimate_workspace_size.argtypes, lib.cldiam_estimate_workspace_size.restype = [I32, I64], SZ
@@ -225,7 +229,7 @@ class DecomposeJob:
     """Reusable decomposition launch: outputs, workspace and descriptors are
     allocated once so that repeated runs time only the device work."""
 
-    def __init__(self, graphs, params, driver=DRIVER_AUTO):
+    def __init__(self, graphs, params, driver=DRIVER_AUTO, local_rounds=-1, grid_blocks=0):
         torch = _torch()
         self.lib = load_library()
         self.graphs = list(graphs)
@@ -243,24 +247,27 @@ class DecomposeJob:
         self.wsb = self.lib.cldiam_decompose_workspace_size(total_n, G)
         self.ws = _ws(self.wsb, dev)
         self.driver = driver
+        self.tuning = _Tuning(local_rounds, grid_blocks)
 
     def run(self, stream=None):
-        _check(self.lib.cldiam_decompose_batch(len(self.graphs), self.desc, self.stats, self.driver, _ptr(self.ws),
-                                               self.wsb, _stream(stream)), "cldiam_decompose_batch")
+        _check(self.lib.cldiam_decompose_batch(len(self.graphs), self.desc, self.stats, self.driver,
+                                               ctypes.byref(self.tuning), _ptr(self.ws), self.wsb, _stream(stream)),
+               "cldiam_decompose_batch")
         return [_stats(s) for s in self.stats]
 
 
-def cldiam_decompose(g: DeviceGraph, tau: int, seed: int, delta0: int = 0, driver=DRIVER_AUTO, stream=None):
+def cldiam_decompose(g: DeviceGraph, tau: int, seed: int, delta0: int = 0, driver=DRIVER_AUTO, stream=None,
+                     local_rounds=-1, grid_blocks=0):
     """CLUSTER(G, tau): returns (cluster int32 tensor, D int64 tensor holding
     uint64 bit patterns, Stats)."""
-    job = DecomposeJob([g], [(tau, seed, delta0)], driver)
+    job = DecomposeJob([g], [(tau, seed, delta0)], driver, local_rounds, grid_blocks)
     st = job.run(stream)
     return job.cluster[0], job.D[0], st[0]
 
 
-def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None):
+def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None, local_rounds=-1, grid_blocks=0):
     """Decomposes many graphs in one device job; params = [(tau, seed, delta0)]."""
-    job = DecomposeJob(graphs, params, driver)
+    job = DecomposeJob(graphs, params, driver, local_rounds, grid_blocks)
     st = job.run(stream)
     return job.cluster, job.D, st
 

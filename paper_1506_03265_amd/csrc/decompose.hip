@@ -154,6 +154,8 @@ struct Job {
 constexpr int kThreads = 1024;
 constexpr int kStageCap = 4096;   // LDS staging slots per output list
 constexpr int kLocalCap = 4096;   // LDS local-round queue slots
+constexpr int kHeavyDeg = 128;    // rows above this degree are relaxed by the whole workgroup
+constexpr int kHeavyCap = 256;    // deferred heavy rows per round
 constexpr int kLocalRounds = 4;   // default local relaxation rounds per RELAX run
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 
@@ -329,6 +331,8 @@ struct Stage {
   int32_t buf[3][kStageCap];
   int32_t lq[2][kLocalCap];  // local relaxation queues
   uint32_t lq_cnt[2];
+  int32_t heavy[kHeavyCap];  // rows deferred to the cooperative pass
+  uint32_t heavy_cnt;
   uint32_t cnt[3];
   uint32_t base[3];
   unsigned long long acc;   // min (NEXT) or max (ASSIGN) accumulator
@@ -389,6 +393,13 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
                                                const Out *out, uint32_t *lq_cnt, int32_t *lq) {
   const int32_t a0 = d.row_ptr[u];
   const int32_t a1 = d.row_ptr[u + 1];
+  if (a1 - a0 > kHeavyDeg) {
+    const uint32_t slot = atomicAdd(&S.heavy_cnt, 1u);
+    if (slot < kHeavyCap) {
+      S.heavy[slot] = u;   // relaxed by relax_heavy after this round
+      return 0;
+    }
+  }
   const uint64_t ku = job.key[off + u];
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
@@ -433,6 +444,55 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
   }
   if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
     stage_push(S, out, 2, u);
+  return scanned;
+}
+
+// Rows deferred by relax_item: the whole workgroup relaxes one row at a time.
+// The light prefix ends at the first arc heavier than Delta - d_u (rows are
+// sorted by weight), found by binary search.
+__device__ uint32_t relax_heavy(const Job &job, const GDesc &d, int64_t off, uint32_t delta, uint32_t it,
+                                uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+  __syncthreads();
+  const uint32_t nh = S.heavy_cnt < kHeavyCap ? S.heavy_cnt : kHeavyCap;
+  uint32_t scanned = 0;
+  for (uint32_t h = 0; h < nh; ++h) {
+    const int32_t u = S.heavy[h];
+    const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
+    const uint64_t ku = job.key[off + u];
+    const uint32_t lim = delta - (uint32_t)(ku >> 32);
+    int32_t lo = a0, hi = a1;  // first index with w > lim
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if ((uint32_t)(d.arcs[mid] >> 32) <= lim) lo = mid + 1; else hi = mid;
+    }
+    const int32_t end = lo;
+    for (int32_t a = a0 + (int32_t)threadIdx.x; a < end; a += (int32_t)blockDim.x) {
+      const uint64_t arc = d.arcs[a];
+      const int32_t v = (int32_t)(uint32_t)arc;
+      const int64_t gv = off + v;
+      const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
+      ++scanned;
+      if (cand < job.key[gv]) {
+        const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
+        if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
+        if (cand < old) {
+          if (old == CLD_INF64) stage_push(S, out, 1, v);
+          if (lq) lq_push(lq_cnt, lq, v);
+        }
+      }
+    }
+    if (threadIdx.x == 0 && end < a1 && job.bstamp[off + u] != level_id &&
+        atomicExch(&job.bstamp[off + u], level_id) != level_id)
+      stage_push(S, out, 2, u);
+    // keep LDS staging within bounds between rows
+    __syncthreads();
+    if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+    __syncthreads();
+    if (S.flush) stage_flush(S, out, 3);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.heavy_cnt = 0;
+  __syncthreads();
   return scanned;
 }
 
@@ -492,6 +552,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.acc32 = 0;
     S.lq_cnt[0] = 0;
     S.lq_cnt[1] = 0;
+    S.heavy_cnt = 0;
   }
   __syncthreads();
   uint32_t scanned = 0;
@@ -554,6 +615,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
       }
     }
+    if (phase == PH_RELAX) scanned += relax_heavy(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[0], S.lq[0]);
     if (nout) {
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -574,6 +636,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
         scanned += relax_item(job, d, off, delta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
+      scanned += relax_heavy(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
       __syncthreads();
@@ -727,20 +790,16 @@ Ctl *host_ctl() {
   return t_host_ctl;
 }
 
-// Workgroups of the sweep grid: one per CU by default; CLDIAM_GRID_BLOCKS
-// overrides (bounded by the co-resident maximum for the persistent kernel).
-int grid_blocks(int driver, int *blocks) {
+// Workgroups of the sweep grid: one per CU unless requested (bounded by the
+// co-resident maximum for the persistent kernel).
+int grid_blocks(int driver, int requested, int *blocks) {
   int coop_blocks = 0;
   int rc = cld::cooperative_blocks((const void *)k_persistent, kThreads, 1, &coop_blocks);
   if (rc) return rc;
   int dev = 0, cus = 0;
   CLD_HIP(hipGetDevice(&dev));
   CLD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int want = cus;
-  if (const char *e = getenv("CLDIAM_GRID_BLOCKS")) {
-    int x = atoi(e);
-    if (x > 0) want = x;
-  }
+  int want = requested > 0 ? requested : cus;
   if (driver == CLDIAM_DRIVER_HOST) {
     *blocks = want;
     return CLDIAM_OK;
@@ -762,8 +821,8 @@ extern "C" size_t cldiam_decompose_workspace_size(int64_t total_n, int32_t num_g
   return s.s.used;
 }
 
-extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_stats *stats, int driver, void *ws,
-                                      size_t ws_bytes, void *stream_) {
+extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_stats *stats, int driver,
+                                      const cldiam_tuning *tuning, void *ws, size_t ws_bytes, void *stream_) {
   hipStream_t stream = (hipStream_t)stream_;
   if (G < 1 || !gs) { cld::set_error("decompose: num_graphs < 1 or no graphs"); return CLDIAM_EINVAL; }
   int64_t N = 0;
@@ -810,8 +869,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = G;
-  job.local_rounds = kLocalRounds;
-  if (const char *e = getenv("CLDIAM_LOCAL_ROUNDS")) job.local_rounds = atoi(e) < 0 ? 0 : atoi(e);
+  job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
+  if (job.local_rounds > 64) job.local_rounds = 64;
 
   CLD_HIP(hipMemcpyAsync(L.desc, desc.data(), sizeof(GDesc) * G, hipMemcpyHostToDevice, stream));
   CLD_HIP(hipMemsetAsync(L.st, 0, sizeof(GState) * G, stream));
@@ -831,7 +890,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
 
   int blocks = 0;
   {
-    int rc = grid_blocks(driver == CLDIAM_DRIVER_PERSISTENT ? driver : CLDIAM_DRIVER_HOST, &blocks);
+    int rc = grid_blocks(driver == CLDIAM_DRIVER_PERSISTENT ? driver : CLDIAM_DRIVER_HOST,
+                         tuning ? tuning->grid_blocks : 0, &blocks);
     if (rc) return rc;
     if (blocks == 0 && driver == CLDIAM_DRIVER_PERSISTENT) {
       cld::set_error("decompose: device has no cooperative launch");
@@ -839,7 +899,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     }
   }
   const bool persistent = driver == CLDIAM_DRIVER_PERSISTENT && blocks > 0;
-  if (!persistent && blocks == 0) blocks = 256;
+  if (!persistent && blocks <= 0) blocks = 256;
+  if (blocks > 65535) blocks = 65535;
   Ctl *hc = host_ctl();
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -928,7 +989,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   return rc;
 }
 
-extern "C" int cldiam_decompose(const cldiam_graph *g, cldiam_stats *stats, int driver, void *ws, size_t ws_bytes,
-                                void *stream) {
-  return cldiam_decompose_batch(1, g, stats, driver, ws, ws_bytes, stream);
+extern "C" int cldiam_decompose(const cldiam_graph *g, cldiam_stats *stats, int driver, const cldiam_tuning *tuning,
+                                void *ws, size_t ws_bytes, void *stream) {
+  return cldiam_decompose_batch(1, g, stats, driver, tuning, ws, ws_bytes, stream);
 }

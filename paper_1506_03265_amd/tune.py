@@ -1,0 +1,87 @@
+"""Schedule autotuner for decomposition jobs.
+
+The knobs it chooses never change results: the driver (host-driven launches
+or one persistent cooperative kernel), the number of workgroup-local
+relaxation rounds per sweep, and the number of workgroups per sweep.  Each
+candidate is timed on the job itself; the outputs of every candidate are
+checked to be identical to the first one's (a schedule that changed a result
+would be a bug).  The choice is cached per workload class (graph count and
+powers of two of the node and arc totals) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import DRIVER_HOST, DRIVER_PERSISTENT, DecomposeJob, _torch
+
+CANDIDATES = (
+    [dict(driver=DRIVER_HOST, local_rounds=r, grid_blocks=0) for r in (0, 2, 4, 8)]
+    + [dict(driver=DRIVER_HOST, local_rounds=4, grid_blocks=128)]
+    + [dict(driver=DRIVER_PERSISTENT, local_rounds=r, grid_blocks=128) for r in (0, 4)]
+)
+
+
+def _cache_path() -> str:
+    return os.environ.get("CLDIAM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "cldiam_tune.json"))
+
+
+def workload_class(graphs) -> str:
+    n = sum(g.n for g in graphs)
+    m = sum(g.m for g in graphs)
+    return f"g{len(graphs)}-n2^{int(math.log2(max(n, 1)))}-m2^{int(math.log2(max(m, 1)))}"
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def tune_batch(graphs, params, reps: int = 2, use_cache: bool = True, candidates=CANDIDATES) -> dict:
+    """Returns the fastest candidate (a dict of DecomposeJob keyword
+    arguments) for this batch, timing each over `reps` runs after one warm-up."""
+    torch = _torch()
+    key = workload_class(graphs)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]["best"]
+    ref = None
+    timings = []
+    for cand in candidates:
+        job = DecomposeJob(graphs, params, **cand)
+        job.run()
+        if ref is None:
+            ref = ([c.clone() for c in job.cluster], [d.clone() for d in job.D])
+        else:
+            for c, d, rc, rd in zip(job.cluster, job.D, ref[0], ref[1]):
+                if not (bool((c == rc).all()) and bool((d == rd).all())):
+                    raise RuntimeError(f"schedule {cand} changed the decomposition")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            job.run()
+        torch.cuda.synchronize()
+        timings.append(((time.perf_counter() - t0) / reps, cand))
+        del job
+    best = min(timings, key=lambda x: x[0])[1]
+    if use_cache:
+        cache[key] = {"best": best, "timings_ms": [[round(t * 1e3, 3), c] for t, c in timings]}
+        _save(cache)
+    return best

@@ -25,6 +25,9 @@ WORKLOADS = {
     "road4096": dict(maker=lambda: graphgen.road_like(4096, 1), tau=4, seed=1,
                      text="road-like 4096x4096 mesh, 5% edges dropped, 1% diagonals, largest component, "
                           "weights uniform in [1, 1e4], graph seed 1"),
+    "rmat24": dict(maker=lambda: graphgen.rmat(24, seed=1), tau=4, seed=1,
+                   text="R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, simple, "
+                        "largest component, weights uniform in [1, 2^20], graph seed 1"),
 }
 
 

@@ -54,7 +54,7 @@ def test_workspace_queries_are_monotone(lib):
 
 def test_invalid_arguments_fail_before_touching_a_device(lib):
     # no graphs at all: rejected by host validation
-    assert lib.cldiam_decompose_batch(0, None, None, 0, None, 0, None) == cd.CLDIAM_EINVAL
+    assert lib.cldiam_decompose_batch(0, None, None, 0, None, None, 0, None) == cd.CLDIAM_EINVAL
     assert b"num_graphs" in lib.cldiam_last_error()
     # null quotient outputs
     assert lib.cldiam_build_quotient(0, 0, None, None, None, None, None, None, None, None, None, None, None, 0,

@@ -1,0 +1,111 @@
+"""GPU tests of the systems layers: batched jobs, schedule knobs, the tuner
+and the serving loop.  Every result is compared exactly: with the oracle, and
+between runs that differ only in scheduling (alone vs in a mix, one job vs one
+job per graph, different knob settings)."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1506_03265_amd as cd
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cd.load_library()
+
+
+@pytest.mark.parametrize("local_rounds,grid_blocks,driver", [(0, 0, 1), (1, 7, 1), (7, 64, 1), (16, 300, 1),
+                                                             (3, 33, 2), (0, 256, 2)])
+def test_schedule_knobs_do_not_change_results(local_rounds, grid_blocks, driver):
+    g = graphgen.road_like(400, 6)
+    _say(f"[systems] knobs rounds={local_rounds} blocks={grid_blocks} driver={driver}")
+    ref = oracle.decompose(g, 2, 9)
+    dg = cd.cldiam_load_csr(g)
+    c, D, st = cd.cldiam_decompose(dg, 2, 9, driver=driver, local_rounds=local_rounds, grid_blocks=grid_blocks)
+    assert np.array_equal(c.cpu().numpy(), ref.cluster)
+    assert np.array_equal(cd.u64(D), ref.D)
+    assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
+
+
+def test_batch_of_geometric_graphs_matches_oracle():
+    sizes = [1000, 1500, 2500, 4000, 7000, 12000, 20000, 30000] * 3
+    graphs = [graphgen.rgg(n, i, 5) for i, n in enumerate(sizes)]
+    params = [(1, (i << 32) | 5, 0) for i in range(len(graphs))]
+    _say(f"[systems] batch of {len(graphs)} geometric graphs")
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    clusters, Ds, stats = cd.cldiam_decompose_batch(dgs, params)
+    for g, c, D, st, (tau, seed, d0) in zip(graphs, clusters, Ds, stats, params):
+        ref = oracle.decompose(g, tau, seed, delta0=d0)
+        assert np.array_equal(c.cpu().numpy(), ref.cluster)
+        assert np.array_equal(cd.u64(D), ref.D)
+        assert st.num_clusters == ref.num_clusters and st.radius == ref.radius
+
+
+def test_tuner_returns_a_candidate_and_checks_equality(tmp_path, monkeypatch):
+    from paper_1506_03265_amd import tune
+    monkeypatch.setenv("CLDIAM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    graphs = [graphgen.rgg(n, i, 2) for i, n in enumerate([3000, 9000, 500])]
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    params = [(1, i + 1, 0) for i in range(3)]
+    best = tune.tune_batch(dgs, params, reps=1)
+    assert best in tune.CANDIDATES
+    assert tune.tune_batch(dgs, params, reps=1) == best   # cached
+    assert (tmp_path / "tune.json").exists()
+
+
+def test_served_results_equal_alone_results():
+    """Continuous batching: each request's cluster ids and distance bounds are
+    the same when it runs in the mix and when it runs alone (tolerance 0)."""
+    from paper_1506_03265_amd import serve
+    pool_graphs = {"grid96": graphgen.grid(96, 96, 10000, 96), "grid200": graphgen.grid(200, 200, 10000, 200),
+                   "rmat12": graphgen.rmat(12, seed=12), "rmat14": graphgen.rmat(14, seed=14),
+                   "road256": graphgen.road_like(256, 3)}
+    pool = {k: cd.cldiam_load_csr(g) for k, g in pool_graphs.items()}
+    keys = sorted(pool)
+    rng = np.random.default_rng(11)
+    reqs = [serve.Request(i, float(t), keys[int(rng.integers(0, len(keys)))], 1, 1000 + i)
+            for i, t in enumerate(np.cumsum(rng.exponential(0.002, size=40)))]
+    _say("[systems] serving 40 requests with 4 workers")
+    mixed, _ = serve.serve(reqs, pool, workers=4, keep_outputs=True)
+    _say("[systems] the same requests one at a time")
+    alone, _ = serve.serve(reqs, pool, workers=1, keep_outputs=True)
+    assert [r.rid for r in mixed] == [r.rid for r in alone] == list(range(40))
+    for a, b, req in zip(mixed, alone, reqs):
+        assert bool((a.cluster == b.cluster).all()) and bool((a.D == b.D).all())
+        assert (a.num_clusters, a.radius, a.phi_approx) == (b.num_clusters, b.radius, b.phi_approx)
+    # and against the oracle for a sample of requests
+    for req, res in list(zip(reqs, mixed))[:6]:
+        g = pool_graphs[req.graph]
+        ref = oracle.decompose(g, req.tau, req.seed)
+        est = oracle.estimate(oracle.quotient(g, ref), ref)
+        assert np.array_equal(res.cluster.cpu().numpy(), ref.cluster)
+        assert res.phi_approx == est.phi_approx
+    assert all(r.latency_s >= 0 for r in mixed)
+
+
+def test_serving_respects_a_tiny_budget():
+    """With a budget below two footprints, requests run one at a time and
+    still all complete with the same results."""
+    from paper_1506_03265_amd import serve
+    g = graphgen.grid(128, 128, 1000, 3)
+    pool = {"g": cd.cldiam_load_csr(g)}
+    fp = serve.footprint_bytes(pool["g"])
+    reqs = [serve.Request(i, 0.0, "g", 1, i) for i in range(6)]
+    res, _ = serve.serve(reqs, pool, workers=4, hbm_budget_bytes=fp + fp // 2)
+    starts = sorted((r.start_s, r.done_s) for r in res)
+    assert all(s1 >= d0 - 1e-6 for (_, d0), (s1, _) in zip(starts, starts[1:]))
+    for r in res:
+        ref = oracle.decompose(g, 1, r.rid)
+        assert r.num_clusters == ref.num_clusters and r.radius == ref.radius

@@ -162,8 +162,19 @@ def test_decompose_overflow_matches_oracle(driver):
     assert e.value.status == cd.CLDIAM_EOVERFLOW
 
 
+def _hub_graph(n=30000, seed=3):
+    """A hub joined to every node plus a path through the leaves: rows far
+    above the per-thread size, relaxed by the whole workgroup."""
+    rng = np.random.default_rng(seed)
+    u = [0] * (n - 1) + list(range(1, n - 1))
+    v = list(range(1, n)) + list(range(2, n))
+    w = list(rng.integers(1, 10**6, size=n - 1)) + list(rng.integers(1, 1000, size=n - 2))
+    return graphgen.csr_from_edges_np(n, u, v, w)
+
+
 MEDIUM = [("road512", lambda: graphgen.road_like(512, 3), 2), ("rmat14", lambda: graphgen.rmat(14, seed=4), 1),
-          ("grid300", lambda: graphgen.grid(300, 257, 10000, 9), 1)]
+          ("grid300", lambda: graphgen.grid(300, 257, 10000, 9), 1), ("rmat17", lambda: graphgen.rmat(17, seed=5), 2),
+          ("hub30k", _hub_graph, 1)]
 
 
 @pytest.mark.parametrize("driver", DRIVERS, ids=DRIVER_IDS)
