@@ -1,6 +1,6 @@
-"""Full-size parity on the benchmark workload (road-like 4096x4096 mesh,
-16.8M nodes, 64.1M arcs, tau = 4, seed 1), in the launch configuration the
-benchmark times.  Expected values were written by the oracle
+"""Full-size parity on the benchmark workloads (road-like 4096x4096 mesh,
+16.8M nodes, 64.1M arcs; R-MAT scale 24, 8.9M nodes, 521M arcs; tau = 4,
+seed 1), in the launch configuration the benchmark times.  Expected values were written by the oracle
 (tests/golden/make_workload_counts.py): per-node outputs are compared through
 SHA-256 digests of the oracle's arrays, plus stage counts, the quotient size
 and the estimate."""
@@ -68,3 +68,30 @@ def test_road4096_invariants_on_samples(road):
     assert np.all(c[centers] == centers)
     assert np.all(d[centers] == 0)
     assert int(d.max()) == st.radius <= sum(st.stage_delta)
+
+
+@pytest.mark.timeout(900)
+def test_rmat24_decompose_quotient_estimate():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    counts = json.load(open(os.path.join(HERE, "golden", "rmat24_counts.json")))
+    print("[fullsize] generating rmat24", file=sys.stderr, flush=True)
+    g = graphgen.rmat(24, seed=1)
+    assert (g.n, g.m) == (counts["n"], counts["m_arcs"])
+    dg = cd.cldiam_load_csr(g)
+    del g
+    print("[fullsize] rmat24 decompose", file=sys.stderr, flush=True)
+    cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"])
+    assert (st.stages, st.levels, st.delta0, st.delta_end) == \
+        (counts["stages"], counts["levels"], counts["delta0"], counts["delta_end"])
+    assert (st.num_clusters, st.singletons, st.radius) == \
+        (counts["num_clusters"], counts["singletons"], counts["radius"])
+    assert st.stage_covered == counts["stage_covered"]
+    assert _digest(cluster.cpu().numpy()) == counts["cluster_sha256"]
+    assert _digest(cd.u64(D)) == counts["D_sha256"]
+    print("[fullsize] rmat24 quotient", file=sys.stderr, flush=True)
+    q = cd.cldiam_build_quotient(dg, cluster, D)
+    assert q.k == counts["quotient_k"] and q.qm == 2 * counts["quotient_edges"]
+    phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
+    assert (phi, approx) == (counts["phi_gc"], counts["phi_approx"])
