@@ -154,8 +154,10 @@ struct Job {
 constexpr int kThreads = 1024;
 constexpr int kStageCap = 4096;   // LDS staging slots per output list
 constexpr int kLocalCap = 4096;   // LDS local-round queue slots
-constexpr int kHeavyDeg = 128;    // rows above this degree are relaxed by the whole workgroup
-constexpr int kHeavyCap = 256;    // deferred heavy rows per round
+constexpr int kMidDeg = 32;       // rows above this degree are relaxed by one wave
+constexpr int kBigDeg = 8192;     // rows above this degree are relaxed by the whole workgroup
+constexpr int kMidCap = 2048;     // deferred wave rows per round
+constexpr int kBigCap = 128;      // deferred workgroup rows per round
 constexpr int kLocalRounds = 4;   // default local relaxation rounds per RELAX run
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 
@@ -331,8 +333,11 @@ struct Stage {
   int32_t buf[3][kStageCap];
   int32_t lq[2][kLocalCap];  // local relaxation queues
   uint32_t lq_cnt[2];
-  int32_t heavy[kHeavyCap];  // rows deferred to the cooperative pass
-  uint32_t heavy_cnt;
+  int32_t mid[kMidCap];      // rows deferred to one wave each
+  int32_t big[kBigCap];      // rows deferred to the whole workgroup
+  uint32_t mid_cnt, big_cnt;
+  unsigned long long blk_min;  // workgroup minimum for the NEXT scan of a big row
+  uint32_t blk_hit;
   uint32_t cnt[3];
   uint32_t base[3];
   unsigned long long acc;   // min (NEXT) or max (ASSIGN) accumulator
@@ -383,6 +388,19 @@ __device__ void stage_flush(Stage &S, const Out *out, int nout) {
 // the workgroup's local queue `lq` (when it has room) for the local rounds.
 constexpr int kArcBatch = 4;
 
+// Queues a long row for the cooperative passes of this round; false when the
+// queue is full (the caller then handles the row itself).
+__device__ __forceinline__ bool defer_row(Stage &S, int32_t u, int32_t deg) {
+  if (deg > kBigDeg) {
+    const uint32_t slot = atomicAdd(&S.big_cnt, 1u);
+    if (slot < kBigCap) { S.big[slot] = u; return true; }
+  } else {
+    const uint32_t slot = atomicAdd(&S.mid_cnt, 1u);
+    if (slot < kMidCap) { S.mid[slot] = u; return true; }
+  }
+  return false;
+}
+
 __device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v) {
   const uint32_t slot = atomicAdd(lq_cnt, 1u);
   if (slot < kLocalCap) lq[slot] = v;
@@ -393,13 +411,7 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
                                                const Out *out, uint32_t *lq_cnt, int32_t *lq) {
   const int32_t a0 = d.row_ptr[u];
   const int32_t a1 = d.row_ptr[u + 1];
-  if (a1 - a0 > kHeavyDeg) {
-    const uint32_t slot = atomicAdd(&S.heavy_cnt, 1u);
-    if (slot < kHeavyCap) {
-      S.heavy[slot] = u;   // relaxed by relax_heavy after this round
-      return 0;
-    }
-  }
+  if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
   const uint64_t ku = job.key[off + u];
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
@@ -447,16 +459,94 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
   return scanned;
 }
 
-// Rows deferred by relax_item: the whole workgroup relaxes one row at a time.
-// The light prefix ends at the first arc heavier than Delta - d_u (rows are
-// sorted by weight), found by binary search.
-__device__ uint32_t relax_heavy(const Job &job, const GDesc &d, int64_t off, uint32_t delta, uint32_t it,
-                                uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+// One arc of a cooperative row: the same offer as in relax_item.
+__device__ __forceinline__ void relax_one(const Job &job, int64_t off, uint64_t ku, uint64_t arc, uint32_t it,
+                                          Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+  const int32_t v = (int32_t)(uint32_t)arc;
+  const int64_t gv = off + v;
+  const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
+  if (cand < job.key[gv]) {
+    const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
+    if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
+    if (cand < old) {
+      if (old == CLD_INF64) stage_push(S, out, 1, v);
+      if (lq) lq_push(lq_cnt, lq, v);
+    }
+  }
+}
+
+__device__ __forceinline__ void mark_blocked(const Job &job, int64_t off, int32_t u, uint32_t level_id, Stage &S,
+                                             const Out *out) {
+  if (job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
+    stage_push(S, out, 2, u);
+}
+
+// NEXT for a short row: smallest d_u + w over its heavy arcs (w > Delta - d_u)
+// into unreached nodes.  Rows are sorted by weight, so the first such arc in
+// ascending order gives the minimum.
+__device__ __forceinline__ uint64_t next_small(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
+                                               int32_t u) {
+  const uint64_t ku = job.key[off + u];
+  const uint32_t du = (uint32_t)(ku >> 32);
+  const uint32_t lim = delta - du;
+  const int32_t a1 = d.row_ptr[u + 1];
+  for (int32_t a = d.row_ptr[u]; a < a1; ++a) {
+    const uint64_t arc = d.arcs[a];
+    const uint32_t w = (uint32_t)(arc >> 32);
+    if (w <= lim) continue;
+    if (job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64) return (uint64_t)du + w;
+  }
+  return CLD_INF64;
+}
+
+// Cooperative passes over the rows deferred in this round: each wave takes
+// whole mid-size rows (64 arcs per step), then the whole workgroup takes each
+// big row (blockDim arcs per step).  mode 0 relaxes the light prefix; mode 1
+// (NEXT) finds the first heavy arc into an unreached node and folds d_u + w
+// into S.acc.
+__device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint32_t delta, uint32_t it,
+                              uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq, int mode) {
   __syncthreads();
-  const uint32_t nh = S.heavy_cnt < kHeavyCap ? S.heavy_cnt : kHeavyCap;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t nm = S.mid_cnt < kMidCap ? S.mid_cnt : kMidCap;
+  const uint32_t nb = S.big_cnt < kBigCap ? S.big_cnt : kBigCap;
   uint32_t scanned = 0;
-  for (uint32_t h = 0; h < nh; ++h) {
-    const int32_t u = S.heavy[h];
+  for (uint32_t r = wave; r < nm; r += nwaves) {
+    const int32_t u = S.mid[r];
+    const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
+    const uint64_t ku = job.key[off + u];
+    const uint32_t lim = delta - (uint32_t)(ku >> 32);
+    if (mode == 0) {
+      for (int32_t base = a0; base < a1; base += 64) {
+        const int32_t a = base + (int32_t)lane;
+        const uint64_t arc = a < a1 ? d.arcs[a] : ~0ull;
+        const bool light = a < a1 && (uint32_t)(arc >> 32) <= lim;
+        if (!__any(light)) break;
+        if (light) {
+          ++scanned;
+          relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq);
+        }
+      }
+      if (lane == 0 && (uint32_t)(d.arcs[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
+    } else {
+      for (int32_t base = a0; base < a1; base += 64) {
+        const int32_t a = base + (int32_t)lane;
+        const uint64_t arc = a < a1 ? d.arcs[a] : 0ull;
+        const uint32_t w = (uint32_t)(arc >> 32);
+        const bool hit = a < a1 && w > lim && job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64;
+        const unsigned long long m = __ballot(hit);
+        if (m) {
+          // first hit in ascending order has the smallest weight
+          const int src = __ffsll((long long)m) - 1;
+          const uint64_t c = (uint64_t)(uint32_t)(ku >> 32) + (uint32_t)(__shfl(arc, src) >> 32);
+          if (lane == 0 && c < S.acc) atomicMin(&S.acc, (unsigned long long)c);
+          break;
+        }
+      }
+    }
+  }
+  for (uint32_t h = 0; h < nb; ++h) {
+    const int32_t u = S.big[h];
     const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
     const uint64_t ku = job.key[off + u];
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
@@ -465,55 +555,42 @@ __device__ uint32_t relax_heavy(const Job &job, const GDesc &d, int64_t off, uin
       const int32_t mid = lo + ((hi - lo) >> 1);
       if ((uint32_t)(d.arcs[mid] >> 32) <= lim) lo = mid + 1; else hi = mid;
     }
-    const int32_t end = lo;
-    for (int32_t a = a0 + (int32_t)threadIdx.x; a < end; a += (int32_t)blockDim.x) {
-      const uint64_t arc = d.arcs[a];
-      const int32_t v = (int32_t)(uint32_t)arc;
-      const int64_t gv = off + v;
-      const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
-      ++scanned;
-      if (cand < job.key[gv]) {
-        const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
-        if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
-        if (cand < old) {
-          if (old == CLD_INF64) stage_push(S, out, 1, v);
-          if (lq) lq_push(lq_cnt, lq, v);
+    if (mode == 0) {
+      for (int32_t a = a0 + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
+        ++scanned;
+        relax_one(job, off, ku, d.arcs[a], it, S, out, lq_cnt, lq);
+      }
+      if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
+      // keep LDS staging within bounds between rows
+      __syncthreads();
+      if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      __syncthreads();
+      if (S.flush) stage_flush(S, out, 3);
+    } else {
+      for (int32_t base = lo; base < a1; base += (int32_t)blockDim.x) {
+        if (threadIdx.x == 0) { S.blk_min = CLD_INF64; S.blk_hit = 0; }
+        __syncthreads();
+        const int32_t a = base + (int32_t)threadIdx.x;
+        if (a < a1) {
+          const uint64_t arc = d.arcs[a];
+          if (job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64) {
+            const uint64_t c = (uint64_t)(uint32_t)(ku >> 32) + (uint32_t)(arc >> 32);
+            atomicMin(&S.blk_min, (unsigned long long)c);
+            S.blk_hit = 1;
+          }
         }
+        __syncthreads();
+        const bool found = S.blk_hit != 0;
+        if (found && threadIdx.x == 0 && S.blk_min < S.acc) atomicMin(&S.acc, S.blk_min);
+        __syncthreads();
+        if (found) break;
       }
     }
-    if (threadIdx.x == 0 && end < a1 && job.bstamp[off + u] != level_id &&
-        atomicExch(&job.bstamp[off + u], level_id) != level_id)
-      stage_push(S, out, 2, u);
-    // keep LDS staging within bounds between rows
-    __syncthreads();
-    if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
-    __syncthreads();
-    if (S.flush) stage_flush(S, out, 3);
   }
   __syncthreads();
-  if (threadIdx.x == 0) S.heavy_cnt = 0;
+  if (threadIdx.x == 0) { S.mid_cnt = 0; S.big_cnt = 0; }
   __syncthreads();
   return scanned;
-}
-
-// NEXT: smallest d_u + w over arcs from blocked node u to unreached nodes.
-__device__ __forceinline__ uint64_t next_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
-                                              int32_t u) {
-  const uint64_t ku = job.key[off + u];
-  const uint32_t du = (uint32_t)(ku >> 32);
-  const uint32_t lim = delta - du;
-  const int32_t a0 = d.row_ptr[u];
-  uint64_t best = CLD_INF64;
-  for (int32_t a = d.row_ptr[u + 1] - 1; a >= a0; --a) {
-    const uint64_t arc = d.arcs[a];
-    const uint32_t w = (uint32_t)(arc >> 32);
-    if (w <= lim) break;
-    if (job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64) {
-      const uint64_t c = (uint64_t)du + w;
-      best = c < best ? c : best;
-    }
-  }
-  return best;
 }
 
 // Items [a, b) of the index space, all of graph g.
@@ -552,7 +629,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.acc32 = 0;
     S.lq_cnt[0] = 0;
     S.lq_cnt[1] = 0;
-    S.heavy_cnt = 0;
+    S.mid_cnt = 0;
+    S.big_cnt = 0;
   }
   __syncthreads();
   uint32_t scanned = 0;
@@ -577,7 +655,10 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
                                 S.lq[0]);
           break;
         case PH_NEXT: {
-          const uint64_t best = next_item(job, d, off, delta, job.pool[blk][off + idx]);
+          const int32_t u = job.pool[blk][off + idx];
+          const int32_t deg = d.row_ptr[u + 1] - d.row_ptr[u];
+          if (deg > kMidDeg && defer_row(S, u, deg)) break;
+          const uint64_t best = next_small(job, d, off, delta, u);
           if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
           break;
         }
@@ -615,7 +696,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
       }
     }
-    if (phase == PH_RELAX) scanned += relax_heavy(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[0], S.lq[0]);
+    if (phase == PH_RELAX || phase == PH_NEXT)
+      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[0], S.lq[0], phase == PH_NEXT);
     if (nout) {
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -636,7 +718,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
         scanned += relax_item(job, d, off, delta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
-      scanned += relax_heavy(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
+      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0);
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
       __syncthreads();

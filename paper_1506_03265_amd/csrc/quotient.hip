@@ -43,44 +43,141 @@ __global__ void k_center_list(const int32_t *cluster, int32_t n, const uint32_t 
     if (cluster[v] == (int32_t)v) qcenter[dense[v]] = (int32_t)v;
 }
 
-// One thread per row; every inter-cluster arc appends (key, weight) through
-// a wave-aggregated reservation.
-__global__ void __launch_bounds__(kT) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n,
-                                             const int32_t *cluster, const uint64_t *D, const uint32_t *dense,
-                                             int kb, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // whole waves iterate together so that the reservation sees every lane
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t u = base + threadIdx.x;
-    int32_t a = 0, a1 = 0, cu = -1;
-    uint64_t du = 0, ka = 0;
-    if (u < n) {
-      a = rp[u];
-      a1 = rp[u + 1];
-      cu = cluster[u];
-      du = D[u];
-      ka = (uint64_t)dense[cu] << kb;
+// Emission of inter-cluster arcs.  Each workgroup takes a contiguous range of
+// rows; rows of up to kEmitThreadDeg arcs are walked by one thread, longer rows
+// are deferred to LDS and walked by one wave (64 arcs per step) or, above
+// kEmitBlockDeg, by the whole workgroup.  Every pair (key, weight) first goes
+// into an LDS hash table of the workgroup that keeps the minimum weight per key
+// (the same minimum the quotient keeps), so only distinct pairs reach global
+// memory: the table is written out, with one global reservation, whenever it
+// is half full after a round and at the end.  A pair that finds no slot after
+// a few probes goes straight to global memory.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitThreadDeg = 16;
+constexpr int kEmitBlockDeg = 4096;
+constexpr int kEmitDefer = 512;     // deferred rows per round
+constexpr int kHashCap = 4096;      // LDS hash slots (power of two)
+constexpr int kHashProbes = 16;
+
+struct EmitState {
+  unsigned long long hkey[kHashCap];
+  unsigned long long hval[kHashCap];
+  int32_t mid[kEmitDefer];
+  int32_t big[kEmitDefer];
+  uint32_t nmid, nbig, used, base, cursor;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
+  uint64_t x = key * 0x9E3779B97F4A7C15ull;
+  return (uint32_t)(x >> 40) & (kHashCap - 1);
+}
+
+__device__ __forceinline__ void emit_pair(EmitState &E, uint64_t key, uint64_t val, uint64_t *keys, uint64_t *vals,
+                                          QCtl *ctl) {
+  uint32_t h = hash_slot(key);
+  for (int p = 0; p < kHashProbes; ++p) {
+    const unsigned long long k = atomicCAS(&E.hkey[h], ~0ull, (unsigned long long)key);
+    if (k == ~0ull) atomicAdd(&E.used, 1u);
+    if (k == ~0ull || k == key) {
+      atomicMin(&E.hval[h], (unsigned long long)val);
+      return;
     }
-    for (;;) {
-      const bool live = a < a1;
-      if (!__any(live)) break;
-      bool emit = false;
-      uint64_t key = 0, val = 0;
-      if (live) {
-        const uint64_t arc = arcs[a];
-        const int32_t v = (int32_t)(uint32_t)arc;
-        const int32_t cv = cluster[v];
-        if (cv != cu) {
-          emit = true;
-          key = ka | (uint64_t)dense[cv];
-          val = (arc >> 32) + du + D[v];
-        }
-        ++a;
-      }
-      const uint32_t slot = cld_wave_reserve(emit, &ctl->pairs);
-      if (emit) { keys[slot] = key; vals[slot] = val; }
+    h = (h + 1) & (kHashCap - 1);
+  }
+  const uint32_t at = atomicAdd(&ctl->pairs, 1u);
+  keys[at] = key;
+  vals[at] = val;
+}
+
+__device__ void hash_flush(EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    E.base = E.used ? atomicAdd(&ctl->pairs, E.used) : 0;
+    E.cursor = 0;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kHashCap; i += blockDim.x) {
+    if (E.hkey[i] != ~0ull) {
+      const uint32_t at = E.base + atomicAdd(&E.cursor, 1u);
+      keys[at] = E.hkey[i];
+      vals[at] = E.hval[i];
+      E.hkey[i] = ~0ull;
+      E.hval[i] = ~0ull;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) E.used = 0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void emit_arc(uint64_t arc, int32_t cu, uint64_t du, uint64_t ka, const int32_t *cluster,
+                                         const uint64_t *D, const uint32_t *dense, EmitState &E, uint64_t *keys,
+                                         uint64_t *vals, QCtl *ctl) {
+  const int32_t v = (int32_t)(uint32_t)arc;
+  const int32_t cv = cluster[v];
+  if (cv != cu) emit_pair(E, ka | (uint64_t)dense[cv], (arc >> 32) + du + D[v], keys, vals, ctl);
+}
+
+__global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n,
+                                                       const int32_t *cluster, const uint64_t *D,
+                                                       const uint32_t *dense, int kb, uint64_t *keys, uint64_t *vals,
+                                                       QCtl *ctl) {
+  __shared__ EmitState E;
+  for (uint32_t i = threadIdx.x; i < kHashCap; i += blockDim.x) { E.hkey[i] = ~0ull; E.hval[i] = ~0ull; }
+  if (threadIdx.x == 0) { E.nmid = 0; E.nbig = 0; E.used = 0; }
+  __syncthreads();
+  const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int64_t r = lo; r < hi; r += blockDim.x) {
+    const int64_t u = r + threadIdx.x;
+    if (u < hi) {
+      const int32_t a0 = rp[u], a1 = rp[u + 1];
+      const int32_t deg = a1 - a0;
+      bool done = false;
+      if (deg > kEmitThreadDeg) {
+        uint32_t *cnt = deg > kEmitBlockDeg ? &E.nbig : &E.nmid;
+        int32_t *lst = deg > kEmitBlockDeg ? E.big : E.mid;
+        const uint32_t slot = atomicAdd(cnt, 1u);
+        if (slot < kEmitDefer) { lst[slot] = (int32_t)u; done = true; }
+      }
+      if (!done) {
+        const int32_t cu = cluster[u];
+        const uint64_t du = D[u];
+        const uint64_t ka = (uint64_t)dense[cu] << kb;
+        for (int32_t a = a0; a < a1; ++a) emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+      }
+    }
+    __syncthreads();
+    const uint32_t nm = E.nmid < kEmitDefer ? E.nmid : kEmitDefer;
+    for (uint32_t i = wave; i < nm; i += nwaves) {
+      const int32_t u = E.mid[i];
+      const int32_t a0 = rp[u], a1 = rp[u + 1];
+      const int32_t cu = cluster[u];
+      const uint64_t du = D[u];
+      const uint64_t ka = (uint64_t)dense[cu] << kb;
+      for (int32_t a = a0 + (int32_t)lane; a < a1; a += 64)
+        emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+    }
+    const uint32_t nbg = E.nbig < kEmitDefer ? E.nbig : kEmitDefer;
+    for (uint32_t i = 0; i < nbg; ++i) {
+      const int32_t u = E.big[i];
+      const int32_t a0 = rp[u], a1 = rp[u + 1];
+      const int32_t cu = cluster[u];
+      const uint64_t du = D[u];
+      const uint64_t ka = (uint64_t)dense[cu] << kb;
+      for (int32_t a = a0 + (int32_t)threadIdx.x; a < a1; a += (int32_t)blockDim.x)
+        emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+      __syncthreads();
+      if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { E.nmid = 0; E.nbig = 0; }
+    __syncthreads();
+    if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
+  }
+  hash_flush(E, keys, vals, ctl);
 }
 
 __global__ void k_heads(const uint64_t *keys, int64_t P, uint32_t *head) {
@@ -93,20 +190,33 @@ __global__ void k_fill_inf(uint64_t *x, int64_t n) {
     x[i] = CLD_INF64;
 }
 
-// Run minimum into the unique slot; heads also write the column and fill the
-// row offsets of every row in (previous row, this row].
+// Run minimum into the unique slot, one chunk of kRunChunk consecutive
+// elements per thread: one atomic per (run, chunk) piece.  Heads also write the
+// column and fill the row offsets of every row in (previous row, this row].
+constexpr int kRunChunk = 64;
+
 __global__ void k_reduce_runs(const uint64_t *keys, const uint64_t *vals, int64_t P, const uint32_t *head,
                               const uint32_t *idx, int kb, int32_t *qcol, uint64_t *qw, int64_t *qrp) {
   const uint64_t bmask = (kb >= 64) ? ~0ull : ((1ull << kb) - 1ull);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t j = idx[i] + head[i] - 1;  // unique slot of this run
-    atomicMin((unsigned long long *)&qw[j], (unsigned long long)vals[i]);
-    if (head[i]) {
-      qcol[j] = (int32_t)(keys[i] & bmask);
-      const int64_t row = (int64_t)(keys[i] >> kb);
-      const int64_t prev = (i == 0) ? -1 : (int64_t)(keys[i - 1] >> kb);
-      for (int64_t r = prev + 1; r <= row; ++r) qrp[r] = j;
+  const int64_t chunks = (P + kRunChunk - 1) / kRunChunk;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = c * kRunChunk, e = b + kRunChunk < P ? b + kRunChunk : P;
+    uint32_t slot = idx[b] + head[b] - 1;
+    uint64_t best = vals[b];
+    for (int64_t i = b; i < e; ++i) {
+      if (head[i]) {
+        if (i > b) atomicMin((unsigned long long *)&qw[slot], (unsigned long long)best);
+        slot = idx[i];
+        best = vals[i];
+        qcol[slot] = (int32_t)(keys[i] & bmask);
+        const int64_t row = (int64_t)(keys[i] >> kb);
+        const int64_t prev = (i == 0) ? -1 : (int64_t)(keys[i - 1] >> kb);
+        for (int64_t r = prev + 1; r <= row; ++r) qrp[r] = slot;
+      } else if (vals[i] < best) {
+        best = vals[i];
+      }
     }
+    atomicMin((unsigned long long *)&qw[slot], (unsigned long long)best);
   }
 }
 
@@ -123,10 +233,13 @@ int bits_for(uint32_t x) {  // bits needed for values 0..x
   return b;
 }
 
+constexpr int kEmitBlocks = 2048;
+
 template <class A>
 void carve(A &a, int32_t n, int64_t m, uint32_t **flag, uint32_t **dense, QCtl **ctl, uint64_t **keys,
-           uint64_t **vals, uint64_t **ktmp, uint64_t **vtmp, uint32_t **head, uint32_t **idx) {
+           uint64_t **vals, uint64_t **ktmp, uint64_t **vtmp, uint32_t **head, uint32_t **idx, uint32_t **emitc) {
   *ctl = a.template take<QCtl>(1);
+  *emitc = nullptr;
   *flag = a.template take<uint32_t>((size_t)n);
   *dense = a.template take<uint32_t>((size_t)n);
   *keys = a.template take<uint64_t>((size_t)m + 1);
@@ -151,7 +264,8 @@ extern "C" size_t cldiam_quotient_workspace_size(int32_t n, int64_t m) {
   uint32_t *f, *d, *h, *x;
   QCtl *c;
   uint64_t *k, *v, *kt, *vt;
-  carve(s, n, m, &f, &d, &c, &k, &v, &kt, &vt, &h, &x);
+  uint32_t *ec;
+  carve(s, n, m, &f, &d, &c, &k, &v, &kt, &vt, &h, &x, &ec);
   size_t extra = cld::radix_ws_bytes(m + 1);
   size_t sc = cld::scan_ws_bytes((int64_t)n > m + 1 ? (int64_t)n : m + 1);
   return s.s.used + (extra > sc ? extra : sc);
@@ -171,7 +285,8 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   uint32_t *flag, *dense, *head, *idx;
   QCtl *ctl;
   uint64_t *keys, *vals, *ktmp, *vtmp;
-  carve(a, n, m, &flag, &dense, &ctl, &keys, &vals, &ktmp, &vtmp, &head, &idx);
+  uint32_t *emitc;
+  carve(a, n, m, &flag, &dense, &ctl, &keys, &vals, &ktmp, &vtmp, &head, &idx, &emitc);
   if (!idx || a.used > ws_bytes) {
     cld::set_error("build_quotient: workspace of %zu bytes, %zu needed", ws_bytes, cldiam_quotient_workspace_size(n, m));
     return CLDIAM_ENOMEM;
@@ -191,8 +306,8 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   const int32_t k = (int32_t)h.k;
   const int kb = bits_for(k > 0 ? (uint32_t)(k - 1) : 0u);
   if (m > 0) {
-    k_emit<<<cld::blocks_for(n, kT, 16384), kT, 0, stream>>>(d_row_ptr, d_arcs, n, d_cluster, d_D,
-                                                                          dense, kb, keys, vals, ctl);
+    const unsigned eb = (unsigned)(n < kEmitBlocks * 64 ? (n + 63) / 64 : kEmitBlocks);
+    k_emit<<<eb, kEmitThreads, 0, stream>>>(d_row_ptr, d_arcs, n, d_cluster, d_D, dense, kb, keys, vals, ctl);
     CLD_LAUNCH_CHECK("k_emit");
   }
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
@@ -214,7 +329,7 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
     uniq = h.uniq;
     k_fill_inf<<<cld::blocks_for(uniq, kT, 8192), kT, 0, stream>>>(d_qw, uniq);
     CLD_LAUNCH_CHECK("k_fill_inf");
-    k_reduce_runs<<<cld::blocks_for(P, kT, 8192), kT, 0, stream>>>(sk, sv, P, head, idx, kb, d_qcol, d_qw,
+    k_reduce_runs<<<cld::blocks_for((P + kRunChunk - 1) / kRunChunk, kT, 8192), kT, 0, stream>>>(sk, sv, P, head, idx, kb, d_qcol, d_qw,
                                                                     d_qrow_ptr);
     CLD_LAUNCH_CHECK("k_reduce_runs");
   }

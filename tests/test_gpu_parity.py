@@ -273,3 +273,21 @@ def test_repeat_runs_are_identical():
     for _ in range(3):
         job.run()
         assert bool((job.cluster[0] == c0).all()) and bool((job.D[0] == d0).all())
+
+
+@pytest.mark.parametrize("name,maker,tau", [("rmat14_singletons", lambda: graphgen.rmat(14, seed=6), 200),
+                                            ("grid512_singletons", lambda: graphgen.grid(512, 512, 50, 8), 3000)],
+                         ids=["rmat14", "grid512"])
+def test_quotient_with_many_clusters(name, maker, tau):
+    """Every node its own cluster (8 tau log2 n > n): G_C is G itself, with
+    far more distinct cluster pairs per workgroup than the LDS table holds."""
+    g = maker()
+    dg, cluster, D, st, ref = _check_decomposition(name, g, tau, 1, cd.DRIVER_AUTO)
+    assert st.num_clusters == g.n
+    q = cd.cldiam_build_quotient(dg, cluster, D)
+    rq = oracle.quotient(g, ref)
+    rrp, rcol, rw = rq.csr()
+    assert q.k == rq.k == g.n
+    assert np.array_equal(q.row_ptr.cpu().numpy(), rrp)
+    assert np.array_equal(q.col.cpu().numpy(), rcol)
+    assert np.array_equal(cd.u64(q.w), rw)
