@@ -12,8 +12,10 @@
 // frontier and the remaining far entries.  Distances are exact (u32, with a
 // u64 overflow check); the schedule only changes the work.
 //
-// One cooperative persistent kernel runs the whole search; a control step by
-// workgroup 0 between sweeps picks the next phase.
+// The host drives the search: it enqueues sweep and control launches in
+// batches and polls a done flag (a persistent kernel with grid barriers is
+// slower on this device, where each workgroup's device-scope fence writes back
+// and invalidates its L2).
 #include <string.h>
 
 #include "common.h"
@@ -24,16 +26,21 @@ constexpr int kT = 256;
 
 enum : uint32_t { S_LIGHT = 0, S_HEAVY = 1, S_MINB = 2, S_SPLIT = 3, S_DONE = 4 };
 
+struct alignas(128) SPad {
+  uint32_t v;
+  uint32_t pad_[31];
+};
+
 struct SCtl {
   uint32_t phase;
   uint32_t sweep_id;
   uint32_t bucket;
   uint32_t far_epoch;
   uint32_t fcur, farcur;
-  uint32_t cntF[2];
-  uint32_t cntR;
-  uint32_t cntFar[2];
-  uint32_t minb;
+  SPad cntF[2];
+  SPad cntR;
+  SPad cntFar[2];
+  SPad minb;
   uint32_t total;
   uint32_t done;
   uint32_t overflow;
@@ -68,33 +75,33 @@ __device__ void s_control(const SJob &j) {
   switch (c->phase) {
     case S_LIGHT:
       c->sweeps++;
-      if (c->cntF[c->fcur ^ 1] > 0) {
-        c->cntF[c->fcur] = 0;
+      if (c->cntF[c->fcur ^ 1].v > 0) {
+        c->cntF[c->fcur].v = 0;
         c->fcur ^= 1;
       } else {
-        c->cntF[c->fcur] = 0;
+        c->cntF[c->fcur].v = 0;
         c->phase = S_HEAVY;
       }
       break;
     case S_HEAVY:
-      c->minb = CLD_INF32;
+      c->minb.v = CLD_INF32;
       c->phase = S_MINB;
       break;
     case S_MINB:
-      if (c->minb == CLD_INF32) {
+      if (c->minb.v == CLD_INF32) {
         c->phase = S_DONE;
       } else {
-        c->bucket = c->minb;
+        c->bucket = c->minb.v;
         c->far_epoch = sweep_id;
-        c->cntFar[c->farcur ^ 1] = 0;
-        c->cntF[c->fcur] = 0;
+        c->cntFar[c->farcur ^ 1].v = 0;
+        c->cntF[c->fcur].v = 0;
         c->phase = S_SPLIT;
       }
       break;
     case S_SPLIT:
-      c->cntFar[c->farcur] = 0;
+      c->cntFar[c->farcur].v = 0;
       c->farcur ^= 1;
-      c->cntR = 0;
+      c->cntR.v = 0;
       c->phase = S_LIGHT;
       break;
     default:
@@ -102,9 +109,9 @@ __device__ void s_control(const SJob &j) {
   }
   uint32_t t = 0;
   switch (c->phase) {
-    case S_LIGHT: t = c->cntF[c->fcur]; break;
-    case S_HEAVY: t = c->cntR; break;
-    case S_MINB: case S_SPLIT: t = c->cntFar[c->farcur]; break;
+    case S_LIGHT: t = c->cntF[c->fcur].v; break;
+    case S_HEAVY: t = c->cntR.v; break;
+    case S_MINB: case S_SPLIT: t = c->cntFar[c->farcur].v; break;
     default: t = 0;
   }
   c->total = t;
@@ -124,9 +131,9 @@ __device__ __forceinline__ void relax(const SJob &j, SCtl *c, uint64_t nd, int32
       else tofar = j.farstamp[v] != far_epoch && atomicExch(&j.farstamp[v], far_epoch) != far_epoch;
     }
   }
-  uint32_t s1 = cld_wave_reserve(tofront, &c->cntF[fnxt]);
+  uint32_t s1 = cld_wave_reserve(tofront, &c->cntF[fnxt].v);
   if (tofront) j.F[fnxt][s1] = v;
-  uint32_t s2 = cld_wave_reserve(tofar, &c->cntFar[farcur]);
+  uint32_t s2 = cld_wave_reserve(tofar, &c->cntFar[farcur].v);
   if (tofar) j.Far[farcur][s2] = v;
 }
 
@@ -140,7 +147,7 @@ __device__ void s_item(const SJob &j, uint32_t i, uint32_t phase, uint32_t it) {
       const int32_t u = j.F[fcur][i];
       const uint64_t du = j.dist[u];
       bool addr = j.rstamp[u] != bucket + 1 && atomicExch(&j.rstamp[u], bucket + 1) != bucket + 1;
-      uint32_t s = cld_wave_reserve(addr, &c->cntR);
+      uint32_t s = cld_wave_reserve(addr, &c->cntR.v);
       if (addr) j.R[s] = u;
       for (int32_t a = j.rp[u]; a < j.rp[u + 1]; ++a) {
         const uint64_t arc = j.arcs[a];
@@ -166,7 +173,7 @@ __device__ void s_item(const SJob &j, uint32_t i, uint32_t phase, uint32_t it) {
       const uint64_t d = j.dist[v];
       if (d >= bucket_end) {
         const uint32_t b = (uint32_t)(d / delta);
-        if (b < c->minb) atomicMin(&c->minb, b);
+        if (b < c->minb.v) atomicMin(&c->minb.v, b);
       }
       break;
     }
@@ -176,9 +183,9 @@ __device__ void s_item(const SJob &j, uint32_t i, uint32_t phase, uint32_t it) {
       const uint64_t b = d / delta;
       const bool tofront = b == bucket && j.fstamp[v] != it && atomicExch(&j.fstamp[v], it) != it;
       const bool tofar = b > bucket && j.farstamp[v] != far_epoch && atomicExch(&j.farstamp[v], far_epoch) != far_epoch;
-      uint32_t s1 = cld_wave_reserve(tofront, &c->cntF[fcur]);
+      uint32_t s1 = cld_wave_reserve(tofront, &c->cntF[fcur].v);
       if (tofront) j.F[fcur][s1] = v;
-      uint32_t s2 = cld_wave_reserve(tofar, &c->cntFar[farcur ^ 1]);
+      uint32_t s2 = cld_wave_reserve(tofar, &c->cntFar[farcur ^ 1].v);
       if (tofar) j.Far[farcur ^ 1][s2] = v;
       break;
     }
@@ -208,22 +215,21 @@ __global__ void __launch_bounds__(kT) k_sssp_init(SJob j, int32_t src, unsigned 
     c->phase = S_LIGHT;
     c->far_epoch = 1;
     c->sweep_id = 1;
-    c->cntF[0] = 1;
+    c->cntF[0].v = 1;
     c->total = 1;
     c->t_limit = t_limit;
     j.F[0][0] = src;
   }
 }
 
-__global__ void __launch_bounds__(kT) k_sssp_persistent(SJob j) {
-  const uint32_t nb = gridDim.x;
-  for (;;) {
-    if (j.ctl->done || j.ctl->timeout) return;
-    s_sweep(j, blockIdx.x, nb);
-    if (!cld_grid_barrier(&j.ctl->bar, &j.ctl->timeout, nb)) return;
-    if (blockIdx.x == 0) s_control(j);
-    if (!cld_grid_barrier(&j.ctl->bar, &j.ctl->timeout, nb)) return;
-  }
+__global__ void __launch_bounds__(kT) k_sssp_sweep(SJob j) {
+  if (j.ctl->done) return;
+  s_sweep(j, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kT) k_sssp_control(SJob j) {
+  if (j.ctl->done) return;
+  s_control(j);
 }
 
 __global__ void __launch_bounds__(kT) k_sssp_max(const uint32_t *dist, int32_t n, unsigned long long *mx) {
@@ -280,24 +286,31 @@ extern "C" int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int32_t *d
   j.n = n;
   j.delta = bucket_delta;
   j.dist = d_dist;
-  int blocks = 0;
-  int rc = cld::cooperative_blocks((const void *)k_sssp_persistent, kT, 4, &blocks);
-  if (rc) return rc;
-  if (blocks == 0) { cld::set_error("sssp: device has no cooperative launch"); return CLDIAM_EHIP; }
-  int dev = 0, khz = 0;
+  int dev = 0, khz = 0, cus = 0;
   CLD_HIP(hipGetDevice(&dev));
   CLD_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  CLD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   if (khz <= 0) khz = 100000;
+  const int blocks = 4 * cus;
   k_sssp_init<<<cld::blocks_for(n, kT, 8192), kT, 0, stream>>>(j, source, (unsigned long long)khz * 1000ull * 60ull);
   CLD_LAUNCH_CHECK("k_sssp_init");
-  void *args[] = {&j};
-  CLD_HIP(hipLaunchCooperativeKernel((const void *)k_sssp_persistent, dim3(blocks), dim3(kT), args, 0, stream));
+  SCtl hc;
+  int batch = 8;
+  for (;;) {
+    for (int i = 0; i < batch; ++i) {
+      k_sssp_sweep<<<blocks, kT, 0, stream>>>(j);
+      k_sssp_control<<<1, 64, 0, stream>>>(j);
+    }
+    CLD_LAUNCH_CHECK("k_sssp_sweep");
+    CLD_HIP(hipMemcpyAsync(&hc, j.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
+    CLD_HIP(hipStreamSynchronize(stream));
+    if (hc.done || hc.timeout) break;
+    if (batch < 128) batch *= 2;
+  }
   CLD_HIP(hipMemsetAsync(mx, 0, 8, stream));
   k_sssp_max<<<cld::blocks_for(n, kT, 4096), kT, 0, stream>>>(d_dist, n, mx);
   CLD_LAUNCH_CHECK("k_sssp_max");
-  SCtl hc;
   unsigned long long hm = 0;
-  CLD_HIP(hipMemcpyAsync(&hc, j.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipMemcpyAsync(&hm, mx, 8, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
   if (hc.timeout) { cld::set_error("sssp: grid barrier timed out"); return CLDIAM_ETIMEOUT; }
