@@ -174,6 +174,33 @@ int cldiam_decompose_batch(int32_t num_graphs, const cldiam_graph *h_graphs, cld
 int cldiam_decompose(const cldiam_graph *h_graph, cldiam_stats *h_stats, int driver, const cldiam_tuning *tuning,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------- continuous-batching server ---
+ * A long-lived decomposition job for request streams.  Requests (one graph
+ * each, same description as a batch entry) are queued by
+ * cldiam_server_submit at any time; every cldiam_server_step admits queued
+ * requests in arrival order while a slot and a free node range of the
+ * workspace are available, advances every admitted graph together by up to
+ * max_sweeps sweeps, and moves the graphs that finished to the completion
+ * list read by cldiam_server_poll.  A finished graph's d_cluster / d_D hold
+ * its results, identical to a cldiam_decompose call on the same graph; its
+ * slot and node range are reused at once.  The server owns no device memory
+ * beyond the caller's workspace (cldiam_server_workspace_size of the node
+ * capacity and slot count); host state is released by cldiam_server_destroy.
+ * A server is used from one host thread at a time. */
+typedef struct cldiam_server cldiam_server;
+size_t cldiam_server_workspace_size(int64_t node_capacity, int32_t max_graphs);
+int cldiam_server_create(cldiam_server **out, int64_t node_capacity, int32_t max_graphs, const cldiam_tuning *tuning,
+                         void *ws, size_t ws_bytes, void *stream);
+void cldiam_server_destroy(cldiam_server *server);
+/* Queues one request; CLDIAM_ENOMEM when the graph can never fit. */
+int cldiam_server_submit(cldiam_server *server, const cldiam_graph *h_graph, uint64_t tag);
+/* Admits, runs up to max_sweeps sweeps, collects finished requests; returns the
+ * numbers of admitted (running) and still queued requests. */
+int cldiam_server_step(cldiam_server *server, int32_t max_sweeps, int32_t *h_active, int32_t *h_queued);
+/* Up to max_done finished requests (tags and statistics, oldest first). */
+int cldiam_server_poll(cldiam_server *server, uint64_t *h_tags, cldiam_stats *h_stats, int32_t max_done,
+                       int32_t *h_ndone);
+
 /* ---------------------------------------------------- quotient graph ---
  * Weighted quotient graph G_C of Section 4: one node per cluster, numbered by
  * ascending center id; for every edge {u,v} of G with c_u != c_v an edge

@@ -36,6 +36,8 @@ EXPORTS = [
     "cldiam_quotient_workspace_size", "cldiam_build_quotient",
     "cldiam_estimate_workspace_size", "cldiam_estimate_diameter",
     "cldiam_sssp_workspace_size", "cldiam_sssp_delta_stepping",
+    "cldiam_server_workspace_size", "cldiam_server_create", "cldiam_server_destroy", "cldiam_server_submit",
+    "cldiam_server_step", "cldiam_server_poll",
 ]
 
 
@@ -102,8 +104,15 @@ def load_library(path: str = LIB_PATH):
     lib.cldiam_estimate_diameter.argtypes = [I32, I64, V, V, V, U64, P(U64), P(U64), V, SZ, V]
     lib.cldiam_sssp_workspace_size.argtypes, lib.cldiam_sssp_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_sssp_delta_stepping.argtypes = [I32, I64, V, V, I32, U32, V, P(U64), V, SZ, V]
+    lib.cldiam_server_workspace_size.argtypes, lib.cldiam_server_workspace_size.restype = [I64, I32], SZ
+    lib.cldiam_server_create.argtypes = [P(V), I64, I32, P(_Tuning), V, SZ, V]
+    lib.cldiam_server_destroy.argtypes, lib.cldiam_server_destroy.restype = [V], None
+    lib.cldiam_server_submit.argtypes = [V, P(_Graph), U64]
+    lib.cldiam_server_step.argtypes = [V, I32, P(I32), P(I32)]
+    lib.cldiam_server_poll.argtypes = [V, P(U64), P(_Stats), I32, P(I32)]
     for name in ("cldiam_load_csr", "cldiam_decompose_batch", "cldiam_decompose", "cldiam_build_quotient",
-                 "cldiam_estimate_diameter", "cldiam_sssp_delta_stepping"):
+                 "cldiam_estimate_diameter", "cldiam_sssp_delta_stepping", "cldiam_server_create",
+                 "cldiam_server_submit", "cldiam_server_step", "cldiam_server_poll"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -270,6 +279,68 @@ def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None, loca
     job = DecomposeJob(graphs, params, driver, local_rounds, grid_blocks)
     st = job.run(stream)
     return job.cluster, job.D, st
+
+
+# ---------------------------------------------------------------- server --
+
+class Server:
+    """Continuous-batching decomposition job (cldiam_server_*): submit requests
+    at any time, step to advance every admitted request together, poll for
+    finished ones.  Output tensors of a request are allocated at submit and
+    handed back by poll."""
+
+    def __init__(self, node_capacity: int, max_graphs: int = 64, local_rounds: int = -1, grid_blocks: int = 0,
+                 device="cuda", stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.wsb = self.lib.cldiam_server_workspace_size(node_capacity, max_graphs)
+        self.ws = _ws(self.wsb, device)
+        self.ptr = ctypes.c_void_p()
+        _check(self.lib.cldiam_server_create(ctypes.byref(self.ptr), node_capacity, max_graphs,
+                                             ctypes.byref(_Tuning(local_rounds, grid_blocks)), _ptr(self.ws), self.wsb,
+                                             ctypes.c_void_p(self.stream.cuda_stream)), "cldiam_server_create")
+        self.outputs = {}
+        self.max_graphs = max_graphs
+
+    def submit(self, g: DeviceGraph, tau: int, seed: int, tag: int, delta0: int = 0):
+        torch = _torch()
+        cluster = torch.empty(g.n, dtype=torch.int32, device=self.device)
+        D = torch.empty(g.n, dtype=torch.int64, device=self.device)
+        desc = _Graph(g.n, 0, g.m, g.row_ptr.data_ptr(), _ptr(g.arcs).value, g.weight_sum,
+                      _Params(tau, delta0, seed), cluster.data_ptr(), D.data_ptr())
+        _check(self.lib.cldiam_server_submit(self.ptr, ctypes.byref(desc), tag), "cldiam_server_submit")
+        self.outputs[tag] = (g, cluster, D)
+
+    def step(self, max_sweeps: int = 8):
+        active, queued = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.cldiam_server_step(self.ptr, max_sweeps, ctypes.byref(active), ctypes.byref(queued)),
+               "cldiam_server_step")
+        return active.value, queued.value
+
+    def poll(self):
+        k = self.max_graphs
+        tags = (ctypes.c_uint64 * k)()
+        stats = (_Stats * k)()
+        nd = ctypes.c_int32()
+        _check(self.lib.cldiam_server_poll(self.ptr, tags, stats, k, ctypes.byref(nd)), "cldiam_server_poll")
+        out = []
+        for i in range(nd.value):
+            g, cluster, D = self.outputs.pop(int(tags[i]))
+            out.append((int(tags[i]), _stats(stats[i]), g, cluster, D))
+        return out
+
+    def close(self):
+        if self.ptr:
+            self.lib.cldiam_server_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------- quotient --

@@ -75,6 +75,7 @@ enum Phase : uint32_t {
   PH_COMPACT = 6,
   PH_SINGLE = 7,
   PH_DONE = 8,
+  PH_IDLE = 9,   // empty slot of a server job
 };
 
 struct GDesc {
@@ -173,10 +174,11 @@ __device__ uint32_t items_of(const GState &s, const GCount &c) {
   }
 }
 
+// A failing graph stops alone; the other graphs of the job go on.
 __device__ void fail(GState &s, Ctl *ctl, int status) {
+  (void)ctl;
   s.status = status;
   s.phase = PH_DONE;
-  atomicCAS(&ctl->error, 0u, (uint32_t)(-status));
 }
 
 __device__ void begin_stage(const GDesc &d, GState &s, GCount &c, Ctl *ctl) {
@@ -301,7 +303,7 @@ __device__ void control_block(const Job &job) {
       if (ctl->error == 0 || job.st[g].phase == PH_DONE) control_graph(job, g, sweep_id);
       if (ctl->error != 0 && job.st[g].phase != PH_DONE) job.st[g].phase = PH_DONE;
       items = items_of(job.st[g], job.cn[g]);
-      if (job.st[g].phase != PH_DONE) atomicAnd(&alldone, 0u);
+      if (job.st[g].phase != PH_DONE && job.st[g].phase != PH_IDLE) atomicAnd(&alldone, 0u);
     }
     scan[threadIdx.x] = items;
     __syncthreads();
@@ -787,6 +789,18 @@ __global__ void __launch_bounds__(256) k_init(Job job, int64_t total_n) {
   }
 }
 
+// Fresh state for one graph of a server job (node range [off, off + n)).
+__global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    job.key[off + i] = CLD_INF64;
+    job.R[off + i] = 0;
+    job.fstamp[off + i] = 0;
+    job.bstamp[off + i] = 0;
+    job.U[0][off + i] = (int32_t)i;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) k_control(Job job) { control_block(job); }
 
 __global__ void __launch_bounds__(kThreads) k_sweep(Job job) {
@@ -894,6 +908,66 @@ int grid_blocks(int driver, int requested, int *blocks) {
   return CLDIAM_OK;
 }
 
+// Descriptor of one graph (node offset set by the caller); returns a status.
+int make_desc(const cldiam_graph &x, int g, GDesc *out) {
+  if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 31) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
+      !x.d_D || x.params.tau < 1) {
+    cld::set_error("decompose: invalid graph %d (n=%d m=%lld tau=%u)", g, x.n, (long long)x.m, x.params.tau);
+    return CLDIAM_EINVAL;
+  }
+  GDesc &d = *out;
+  memset(&d, 0, sizeof d);
+  d.row_ptr = x.d_row_ptr;
+  d.arcs = x.d_arcs;
+  d.cluster = x.d_cluster;
+  d.D = x.d_D;
+  d.n = x.n;
+  const double gamma = 4.0 * M_LN2;
+  const double L = log2((double)x.n);
+  d.K = gamma * x.params.tau * L;
+  d.stop = (uint32_t)ceil(8.0 * x.params.tau * L);
+  d.seed = x.params.seed;
+  uint64_t d0 = x.params.delta0;
+  if (d0 == 0) d0 = x.m > 0 ? x.weight_sum / (uint64_t)x.m : 1;
+  if (d0 < 1) d0 = 1;
+  if (d0 > CLD_DELTA_MAX) {
+    cld::set_error("decompose: initial Delta %llu above 2^31 (graph %d)", (unsigned long long)d0, g);
+    return CLDIAM_EOVERFLOW;
+  }
+  d.delta0 = (uint32_t)d0;
+  return CLDIAM_OK;
+}
+
+void fill_stats(const GDesc &d, const GState &st, const GCount &cn, const int32_t *log, cldiam_stats *o) {
+  memset(o, 0, sizeof *o);
+  o->stages = (int32_t)st.stage;
+  o->levels = (int32_t)st.levels;
+  o->delta0 = d.delta0;
+  o->delta_end = st.delta;
+  o->stop = (int32_t)d.stop;
+  o->num_clusters = (int32_t)(st.centers_total + st.singletons);
+  o->singletons = (int32_t)st.singletons;
+  o->sweeps = (int32_t)st.sweeps;
+  o->radius = cn.radius.v;
+  o->status = st.status;
+  for (int s = 0; s < CLDIAM_STAGE_LOG && s < o->stages; ++s) {
+    const int32_t *l = log + (size_t)s * 4;
+    o->stage_uncovered[s] = l[0];
+    o->stage_centers[s] = l[1];
+    o->stage_covered[s] = l[2];
+    o->stage_delta[s] = (uint32_t)l[3];
+  }
+}
+
+int read_wall_limit(unsigned long long *limit) {
+  int dev = 0, khz = 0;
+  CLD_HIP(hipGetDevice(&dev));
+  CLD_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) khz = 100000;
+  *limit = (unsigned long long)khz * 1000ull * kJobSeconds;
+  return CLDIAM_OK;
+}
+
 }  // namespace
 
 extern "C" size_t cldiam_decompose_workspace_size(int64_t total_n, int32_t num_graphs) {
@@ -909,35 +983,11 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   if (G < 1 || !gs) { cld::set_error("decompose: num_graphs < 1 or no graphs"); return CLDIAM_EINVAL; }
   int64_t N = 0;
   std::vector<GDesc> desc(G);
-  const double gamma = 4.0 * M_LN2;
   for (int g = 0; g < G; ++g) {
-    const cldiam_graph &x = gs[g];
-    if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 31) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
-        !x.d_D || x.params.tau < 1) {
-      cld::set_error("decompose: invalid graph %d (n=%d m=%lld tau=%u)", g, x.n, (long long)x.m, x.params.tau);
-      return CLDIAM_EINVAL;
-    }
-    GDesc &d = desc[g];
-    memset(&d, 0, sizeof d);
-    d.row_ptr = x.d_row_ptr;
-    d.arcs = x.d_arcs;
-    d.cluster = x.d_cluster;
-    d.D = x.d_D;
-    d.off = N;
-    d.n = x.n;
-    const double L = log2((double)x.n);
-    d.K = gamma * x.params.tau * L;
-    d.stop = (uint32_t)ceil(8.0 * x.params.tau * L);
-    d.seed = x.params.seed;
-    uint64_t d0 = x.params.delta0;
-    if (d0 == 0) d0 = x.m > 0 ? x.weight_sum / (uint64_t)x.m : 1;
-    if (d0 < 1) d0 = 1;
-    if (d0 > CLD_DELTA_MAX) {
-      cld::set_error("decompose: initial Delta %llu above 2^31 (graph %d)", (unsigned long long)d0, g);
-      return CLDIAM_EOVERFLOW;
-    }
-    d.delta0 = (uint32_t)d0;
-    N += x.n;
+    int rc = make_desc(gs[g], g, &desc[g]);
+    if (rc) return rc;
+    desc[g].off = N;
+    N += gs[g].n;
   }
   if (N >= ((int64_t)1 << 31)) { cld::set_error("decompose: more than 2^31 nodes in one job"); return CLDIAM_EINVAL; }
   Layout L;
@@ -1040,29 +1090,11 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
       cld::set_error("decompose: graph %d failed: %s", g, cldiam_strerror(rc));
     }
     if (!stats) continue;
-    cldiam_stats &o = stats[g];
-    memset(&o, 0, sizeof o);
-    o.stages = (int32_t)st[g].stage;
-    o.levels = (int32_t)st[g].levels;
-    o.delta0 = desc[g].delta0;
-    o.delta_end = st[g].delta;
-    o.stop = (int32_t)desc[g].stop;
-    o.num_clusters = (int32_t)(st[g].centers_total + st[g].singletons);
-    o.singletons = (int32_t)st[g].singletons;
-    o.sweeps = (int32_t)st[g].sweeps;
-    o.radius = cn[g].radius.v;
-    o.arcs_scanned = (G == 1) ? hc->arcs.v : 0;
-    o.status = st[g].status;
-    o.grid_blocks = blocks;
-    o.kernel_ms = kernel_ms;
-    o.iterations = (int32_t)hc->iterations;
-    for (int s = 0; s < CLDIAM_STAGE_LOG && s < o.stages; ++s) {
-      const int32_t *l = &lg[((size_t)g * CLDIAM_STAGE_LOG + s) * 4];
-      o.stage_uncovered[s] = l[0];
-      o.stage_centers[s] = l[1];
-      o.stage_covered[s] = l[2];
-      o.stage_delta[s] = (uint32_t)l[3];
-    }
+    fill_stats(desc[g], st[g], cn[g], &lg[(size_t)g * CLDIAM_STAGE_LOG * 4], &stats[g]);
+    stats[g].arcs_scanned = (G == 1) ? hc->arcs.v : 0;
+    stats[g].grid_blocks = blocks;
+    stats[g].kernel_ms = kernel_ms;
+    stats[g].iterations = (int32_t)hc->iterations;
   }
   if (rc == CLDIAM_OK && hc->error) {
     rc = -(int)hc->error;
@@ -1074,4 +1106,238 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
 extern "C" int cldiam_decompose(const cldiam_graph *g, cldiam_stats *stats, int driver, const cldiam_tuning *tuning,
                                 void *ws, size_t ws_bytes, void *stream) {
   return cldiam_decompose_batch(1, g, stats, driver, tuning, ws, ws_bytes, stream);
+}
+
+// ----------------------------------------------------------- server job --
+// A long-lived decomposition job with graph slots: requests are queued by
+// cldiam_server_submit, admitted between sweeps when a slot and a node range
+// of the workspace are free, advanced together with every other active graph,
+// and released as soon as they finish.
+
+struct cldiam_server {
+  Layout L;
+  Job job;
+  int64_t ncap;
+  int32_t gcap;
+  hipStream_t stream;
+  int blocks;
+  std::vector<GDesc> desc;
+  std::vector<uint64_t> tag;
+  std::vector<char> active;
+  std::vector<std::pair<int64_t, int64_t>> free_ranges;  // (offset, length), sorted by offset
+  struct Pending {
+    GDesc d;
+    uint64_t tag;
+  };
+  std::vector<Pending> queue;
+  size_t qhead = 0;
+  struct Done {
+    uint64_t tag;
+    cldiam_stats st;
+  };
+  std::vector<Done> done;
+  std::vector<GState> st_host;
+  Ctl *hc = nullptr;
+};
+
+namespace {
+
+bool take_range(cldiam_server *s, int64_t n, int64_t *off) {
+  for (size_t i = 0; i < s->free_ranges.size(); ++i) {
+    auto &r = s->free_ranges[i];
+    if (r.second >= n) {
+      *off = r.first;
+      r.first += n;
+      r.second -= n;
+      if (r.second == 0) s->free_ranges.erase(s->free_ranges.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void give_range(cldiam_server *s, int64_t off, int64_t n) {
+  auto &fr = s->free_ranges;
+  auto it = std::lower_bound(fr.begin(), fr.end(), std::make_pair(off, (int64_t)0));
+  it = fr.insert(it, {off, n});
+  size_t i = it - fr.begin();
+  if (i + 1 < fr.size() && fr[i].first + fr[i].second == fr[i + 1].first) {
+    fr[i].second += fr[i + 1].second;
+    fr.erase(fr.begin() + i + 1);
+  }
+  if (i > 0 && fr[i - 1].first + fr[i - 1].second == fr[i].first) {
+    fr[i - 1].second += fr[i].second;
+    fr.erase(fr.begin() + i);
+  }
+}
+
+}  // namespace
+
+extern "C" size_t cldiam_server_workspace_size(int64_t node_capacity, int32_t max_graphs) {
+  return cldiam_decompose_workspace_size(node_capacity, max_graphs);
+}
+
+extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, int32_t max_graphs,
+                                    const cldiam_tuning *tuning, void *ws, size_t ws_bytes, void *stream) {
+  if (!out || node_capacity < 1 || node_capacity >= ((int64_t)1 << 31) || max_graphs < 1 || max_graphs > 65536) {
+    cld::set_error("server: invalid capacity");
+    return CLDIAM_EINVAL;
+  }
+  *out = nullptr;
+  cldiam_server *s = new cldiam_server();
+  PtrArena pa(ws, ws_bytes);
+  if (!carve(pa, node_capacity, max_graphs, &s->L) || pa.a.used > ws_bytes) {
+    delete s;
+    cld::set_error("server: workspace of %zu bytes, %zu needed", ws_bytes,
+                   cldiam_decompose_workspace_size(node_capacity, max_graphs));
+    return CLDIAM_ENOMEM;
+  }
+  s->ncap = node_capacity;
+  s->gcap = max_graphs;
+  s->stream = (hipStream_t)stream;
+  Job &job = s->job;
+  const Layout &L = s->L;
+  job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
+  job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
+  job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = max_graphs;
+  job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
+  if (job.local_rounds > 64) job.local_rounds = 64;
+  int rc = grid_blocks(CLDIAM_DRIVER_HOST, tuning ? tuning->grid_blocks : 0, &s->blocks);
+  if (rc) { delete s; return rc; }
+  if (s->blocks <= 0) s->blocks = 256;
+  s->desc.assign(max_graphs, GDesc{});
+  s->tag.assign(max_graphs, 0);
+  s->active.assign(max_graphs, 0);
+  s->free_ranges.push_back({0, node_capacity});
+  s->st_host.assign(max_graphs, GState{});
+  for (auto &g : s->st_host) g.phase = PH_IDLE;
+  void *p = nullptr;
+  if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    delete s;
+    cld::set_error("server: pinned host buffer allocation failed");
+    return CLDIAM_EHIP;
+  }
+  s->hc = (Ctl *)p;
+  unsigned long long limit = 0;
+  rc = read_wall_limit(&limit);
+  if (rc) { cldiam_server_destroy(s); return rc; }
+  hipStream_t st = s->stream;
+  if (hipMemcpyAsync(L.desc, s->desc.data(), sizeof(GDesc) * max_graphs, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(L.st, s->st_host.data(), sizeof(GState) * max_graphs, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemsetAsync(L.cn, 0, sizeof(GCount) * max_graphs, st) != hipSuccess ||
+      hipMemsetAsync(L.ctl, 0, sizeof(Ctl), st) != hipSuccess ||
+      hipMemcpyAsync(&L.ctl->t_limit, &limit, sizeof limit, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    cldiam_server_destroy(s);
+    cld::set_error("server: initialisation failed");
+    return CLDIAM_EHIP;
+  }
+  *out = s;
+  return CLDIAM_OK;
+}
+
+extern "C" void cldiam_server_destroy(cldiam_server *s) {
+  if (!s) return;
+  if (s->hc) (void)hipHostFree(s->hc);
+  delete s;
+}
+
+extern "C" int cldiam_server_submit(cldiam_server *s, const cldiam_graph *g, uint64_t tag) {
+  if (!s || !g) { cld::set_error("server: null argument"); return CLDIAM_EINVAL; }
+  if (g->n > s->ncap) { cld::set_error("server: graph of %d nodes above the capacity %lld", g->n, (long long)s->ncap); return CLDIAM_ENOMEM; }
+  cldiam_server::Pending p;
+  int rc = make_desc(*g, 0, &p.d);
+  if (rc) return rc;
+  p.tag = tag;
+  s->queue.push_back(p);
+  return CLDIAM_OK;
+}
+
+extern "C" int cldiam_server_step(cldiam_server *s, int32_t max_sweeps, int32_t *h_active, int32_t *h_queued) {
+  if (!s || max_sweeps < 0) { cld::set_error("server: invalid step"); return CLDIAM_EINVAL; }
+  hipStream_t stream = s->stream;
+  Job &job = s->job;
+  // admit queued graphs in arrival order while a slot and a node range are free
+  while (s->qhead < s->queue.size()) {
+    int slot = -1;
+    for (int g = 0; g < s->gcap; ++g)
+      if (!s->active[g]) { slot = g; break; }
+    if (slot < 0) break;
+    cldiam_server::Pending &p = s->queue[s->qhead];
+    int64_t off = 0;
+    if (!take_range(s, p.d.n, &off)) break;
+    p.d.off = off;
+    s->desc[slot] = p.d;
+    s->tag[slot] = p.tag;
+    s->active[slot] = 1;
+    GState fresh{};
+    fresh.phase = PH_START;
+    CLD_HIP(hipMemcpyAsync(&s->L.desc[slot], &s->desc[slot], sizeof(GDesc), hipMemcpyHostToDevice, stream));
+    CLD_HIP(hipMemcpyAsync(&job.st[slot], &fresh, sizeof(GState), hipMemcpyHostToDevice, stream));
+    CLD_HIP(hipMemsetAsync(&job.cn[slot], 0, sizeof(GCount), stream));
+    CLD_HIP(hipMemsetAsync(job.log + (size_t)slot * CLDIAM_STAGE_LOG * 4, 0, sizeof(int32_t) * CLDIAM_STAGE_LOG * 4,
+                           stream));
+    k_init_range<<<cld::blocks_for(p.d.n, 256, 4096), 256, 0, stream>>>(job, off, p.d.n);
+    CLD_LAUNCH_CHECK("k_init_range");
+    // the host copies above read s->desc / fresh before the next host write
+    CLD_HIP(hipStreamSynchronize(stream));
+    s->qhead++;
+  }
+  if (s->qhead > 1024 && s->qhead * 2 > s->queue.size()) {
+    s->queue.erase(s->queue.begin(), s->queue.begin() + s->qhead);
+    s->qhead = 0;
+  }
+  int nactive = 0;
+  for (int g = 0; g < s->gcap; ++g) nactive += s->active[g];
+  if (nactive > 0 && max_sweeps > 0) {
+    CLD_HIP(hipMemsetAsync(&job.ctl->iterations, 0, sizeof(uint32_t), stream));
+    for (int i = 0; i < max_sweeps; ++i) {
+      k_control<<<1, kThreads, 0, stream>>>(job);
+      k_sweep<<<s->blocks, kThreads, 0, stream>>>(job);
+    }
+    CLD_LAUNCH_CHECK("k_sweep");
+    CLD_HIP(hipMemcpyAsync(s->st_host.data(), job.st, sizeof(GState) * s->gcap, hipMemcpyDeviceToHost, stream));
+    CLD_HIP(hipMemcpyAsync(s->hc, job.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    CLD_HIP(hipStreamSynchronize(stream));
+    if (s->hc->error) {
+      cld::set_error("server: device reported %s", cldiam_strerror(-(int)s->hc->error));
+      return -(int)s->hc->error;
+    }
+    for (int g = 0; g < s->gcap; ++g) {
+      if (!s->active[g] || s->st_host[g].phase != PH_DONE) continue;
+      GCount cn;
+      std::vector<int32_t> lg(CLDIAM_STAGE_LOG * 4);
+      CLD_HIP(hipMemcpyAsync(&cn, &job.cn[g], sizeof cn, hipMemcpyDeviceToHost, stream));
+      CLD_HIP(hipMemcpyAsync(lg.data(), job.log + (size_t)g * CLDIAM_STAGE_LOG * 4, sizeof(int32_t) * lg.size(),
+                             hipMemcpyDeviceToHost, stream));
+      const GState idle = [] { GState x{}; x.phase = PH_IDLE; return x; }();
+      CLD_HIP(hipMemcpyAsync(&job.st[g], &idle, sizeof(GState), hipMemcpyHostToDevice, stream));
+      CLD_HIP(hipStreamSynchronize(stream));
+      cldiam_server::Done dn;
+      dn.tag = s->tag[g];
+      fill_stats(s->desc[g], s->st_host[g], cn, lg.data(), &dn.st);
+      s->done.push_back(dn);
+      s->active[g] = 0;
+      give_range(s, s->desc[g].off, s->desc[g].n);
+      --nactive;
+    }
+  }
+  if (h_active) *h_active = nactive;
+  if (h_queued) *h_queued = (int32_t)(s->queue.size() - s->qhead);
+  return CLDIAM_OK;
+}
+
+extern "C" int cldiam_server_poll(cldiam_server *s, uint64_t *h_tags, cldiam_stats *h_stats, int32_t max_done,
+                                  int32_t *h_ndone) {
+  if (!s || !h_ndone || max_done < 0) { cld::set_error("server: invalid poll"); return CLDIAM_EINVAL; }
+  int32_t k = 0;
+  while (k < max_done && k < (int32_t)s->done.size()) {
+    if (h_tags) h_tags[k] = s->done[k].tag;
+    if (h_stats) h_stats[k] = s->done[k].st;
+    ++k;
+  }
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  *h_ndone = k;
+  return CLDIAM_OK;
 }

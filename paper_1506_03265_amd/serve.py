@@ -12,6 +12,13 @@ memory.
 
 `serve(..., workers=1)` is the plain sequential baseline: one request at a
 time, in arrival order.
+
+`serve_engine` batches inside the device job instead: one long-lived
+decomposition job (the cldiam_server_* calls) holds graph slots; a request
+joins at the next sweep boundary when a slot and a node range of the job's
+workspace are free, every admitted request advances in the same sweeps, and a
+finished one leaves at once, its quotient and estimate built by worker threads
+on their own streams.
 """
 from __future__ import annotations
 
@@ -45,6 +52,7 @@ class Result:
     stages: int
     cluster: object = None   # device tensor when kept
     D: object = None
+    status: int = 0          # a decomposition status other than CLDIAM_OK leaves the estimate at 0
 
     @property
     def latency_s(self) -> float:
@@ -168,3 +176,95 @@ def percentile(xs, p: float) -> float:
         return 0.0
     k = min(len(s) - 1, max(0, int(round(p / 100.0 * (len(s) - 1)))))
     return s[k]
+
+
+def serve_engine(requests, graphs: dict, max_graphs: int = 64, node_capacity: int = 0, sweeps_per_step: int = 4,
+                 workers: int = 4, keep_outputs: bool = False, time_scale: float = 1.0, local_rounds: int = -1):
+    """Continuous batching inside one device job: arrived requests are
+    submitted to a cldiam server (admitted between sweeps as slots and node
+    ranges free up, all admitted requests advancing together), finished
+    decompositions go to `workers` threads that build the quotient and the
+    estimate on their own streams.  Returns (results sorted by request id,
+    wall seconds)."""
+    import queue as _queue
+
+    from . import Server
+
+    torch = _torch()
+    reqs = sorted(requests, key=lambda r: r.arrival_s)
+    if node_capacity <= 0:
+        node_capacity = max(sum(sorted((g.n for g in graphs.values()), reverse=True)[:8]),
+                            max(g.n for g in graphs.values()))
+    server = Server(node_capacity, max_graphs, local_rounds=local_rounds)
+    work = _queue.Queue()
+    results, errors = [], []
+    lock = threading.Lock()
+    by_id = {r.rid: r for r in reqs}
+    t_start = time.perf_counter()
+
+    def worker():
+        stream = torch.cuda.Stream()
+        est = None
+        while True:
+            item = work.get()
+            if item is None:
+                return
+            rid, st, g, cluster, D, t_dec = item
+            try:
+                req = by_id[rid]
+                if st.status != 0:
+                    r = Result(rid, req.arrival_s * time_scale, t_dec - t_start, time.perf_counter() - t_start, 0, 0,
+                               0, 0, st.stages, status=st.status)
+                    with lock:
+                        results.append(r)
+                    continue
+                with torch.cuda.stream(stream):
+                    q = QuotientJob(g).run(cluster, D, stream)
+                    if est is None:
+                        est = EstimateJob(q.k, q.qm, g.row_ptr.device)
+                    phi, approx = est.run(q, st.radius, stream)
+                t1 = time.perf_counter()
+                r = Result(rid, req.arrival_s * time_scale, t_dec - t_start, t1 - t_start, st.num_clusters,
+                           st.radius, phi, approx, st.stages, cluster if keep_outputs else None,
+                           D if keep_outputs else None)
+                with lock:
+                    results.append(r)
+            except BaseException as e:
+                with lock:
+                    errors.append(e)
+
+    threads = [threading.Thread(target=worker, daemon=True) for _ in range(workers)]
+    for th in threads:
+        th.start()
+    i, n_total = 0, len(reqs)
+    try:
+        while True:
+            now = time.perf_counter() - t_start
+            while i < n_total and reqs[i].arrival_s * time_scale <= now:
+                r = reqs[i]
+                server.submit(graphs[r.graph], r.tau, r.seed, r.rid)
+                i += 1
+            if server.outputs:   # submitted and not yet polled
+                active, queued = server.step(sweeps_per_step)
+                t_dec = time.perf_counter()
+                for tag, st, g, cluster, D in server.poll():
+                    work.put((tag, st, g, cluster, D, t_dec))
+            with lock:
+                finished = len(results) + len(errors)
+            if finished >= n_total or errors:
+                break
+            if not server.outputs:
+                if i < n_total:
+                    time.sleep(max(0.0, min(0.002, reqs[i].arrival_s * time_scale - (time.perf_counter() - t_start))))
+                else:
+                    time.sleep(0.0005)
+    finally:
+        for _ in threads:
+            work.put(None)
+        for th in threads:
+            th.join()
+        server.close()
+    wall = time.perf_counter() - t_start
+    if errors:
+        raise errors[0]
+    return sorted(results, key=lambda r: r.rid), wall

@@ -109,3 +109,84 @@ def test_serving_respects_a_tiny_budget():
     for r in res:
         ref = oracle.decompose(g, 1, r.rid)
         assert r.num_clusters == ref.num_clusters and r.radius == ref.radius
+
+
+def test_server_matches_oracle_with_slot_and_range_reuse():
+    """In-engine continuous batching: requests submitted while others run,
+    more requests than slots and node ranges, finished slots and ranges handed
+    to queued ones; each result equals the oracle's exactly."""
+    sizes = [800, 5000, 1200, 9000, 300, 2500, 7000, 4000, 600, 9000, 1, 2]
+    graphs = [graphgen.rgg(n, i, 3) if n > 2 else graphgen.csr_from_edges_np(n, [0] * (n - 1), [1] * (n - 1), [5] * (n - 1))
+              for i, n in enumerate(sizes)]
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    srv = cd.Server(12000, max_graphs=3, local_rounds=2)
+    _say(f"[systems] server: {len(graphs)} requests, 3 slots, 12000 nodes")
+    for i in range(5):
+        srv.submit(dgs[i], 1 + i % 2, 100 + i, i)
+    got, steps = {}, 0
+    while len(got) < len(graphs):
+        srv.step(3)
+        for tag, st, g, c, D in srv.poll():
+            got[tag] = (st, c.cpu().numpy(), cd.u64(D))
+        steps += 1
+        if steps == 4:
+            for i in range(5, len(graphs)):
+                srv.submit(dgs[i], 1 + i % 2, 100 + i, i)
+        assert steps < 200000
+    srv.close()
+    for i, g in enumerate(graphs):
+        st, c, D = got[i]
+        ref = oracle.decompose(g, 1 + i % 2, 100 + i)
+        assert st.status == cd.CLDIAM_OK
+        assert np.array_equal(c, ref.cluster), i
+        assert np.array_equal(D, ref.D), i
+        assert (st.stages, st.levels, st.num_clusters, st.radius) == (ref.stages, ref.levels, ref.num_clusters,
+                                                                       ref.radius)
+
+
+def test_server_isolates_a_failing_request():
+    """A request whose Delta overflows finishes alone with EOVERFLOW in its
+    statistics; the requests beside it are unaffected."""
+    n = 128
+    bad = graphgen.csr_from_edges_np(n, range(n - 1), range(1, n), [2**31] * (n - 1))
+    good = [graphgen.grid(40, 40, 1000, 4), graphgen.rmat(11, seed=2)]
+    srv = cd.Server(8000, max_graphs=4)
+    srv.submit(cd.cldiam_load_csr(good[0]), 1, 7, 0)
+    srv.submit(cd.cldiam_load_csr(bad), 1, 1, 1, delta0=2**31)
+    srv.submit(cd.cldiam_load_csr(good[1]), 2, 9, 2)
+    with pytest.raises(cd.CldiamError):
+        srv.submit(cd.cldiam_load_csr(graphgen.grid(100, 100, 10, 1)), 1, 1, 3)   # above the node capacity
+    got, steps = {}, 0
+    while len(got) < 3:
+        srv.step(4)
+        for tag, st, g, c, D in srv.poll():
+            got[tag] = (st, c.cpu().numpy())
+        steps += 1
+        assert steps < 100000
+    srv.close()
+    assert got[1][0].status == cd.CLDIAM_EOVERFLOW
+    for tag, g, tau, seed in ((0, good[0], 1, 7), (2, good[1], 2, 9)):
+        ref = oracle.decompose(g, tau, seed)
+        assert got[tag][0].status == cd.CLDIAM_OK and np.array_equal(got[tag][1], ref.cluster)
+
+
+def test_engine_serving_equals_alone_results():
+    """serve_engine: each request's outputs equal those of the same request run
+    alone through the plain sequential loop."""
+    from paper_1506_03265_amd import serve
+    pool_graphs = {"grid96": graphgen.grid(96, 96, 10000, 96), "rmat12": graphgen.rmat(12, seed=12),
+                   "rmat14": graphgen.rmat(14, seed=14), "road256": graphgen.road_like(256, 3)}
+    pool = {k: cd.cldiam_load_csr(g) for k, g in pool_graphs.items()}
+    keys = sorted(pool)
+    rng = np.random.default_rng(5)
+    reqs = [serve.Request(i, float(t), keys[int(rng.integers(0, len(keys)))], 1 + i % 2, 2000 + i)
+            for i, t in enumerate(np.cumsum(rng.exponential(0.001, size=30)))]
+    _say("[systems] engine serving of 30 requests")
+    eng, _ = serve.serve_engine(reqs, pool, max_graphs=8, keep_outputs=True)
+    alone, _ = serve.serve(reqs, pool, workers=1, keep_outputs=True)
+    assert [r.rid for r in eng] == list(range(30))
+    for a, b in zip(eng, alone):
+        assert a.status == 0
+        assert bool((a.cluster == b.cluster).all()) and bool((a.D == b.D).all())
+        assert (a.num_clusters, a.radius, a.phi_gc, a.phi_approx) == (b.num_clusters, b.radius, b.phi_gc, b.phi_approx)
+        assert a.latency_s >= 0
