@@ -139,7 +139,8 @@ struct Job {
   GState *st;
   GCount *cn;
   Ctl *ctl;
-  uint32_t *seg;     // G + 1 exclusive prefix of per-graph sweep items
+  uint32_t *seg;     // [0, G]: exclusive prefix of per-graph work chunks; [G+1, 2G]: items per chunk;
+                     // [2G+1, 3G]: items of the graph in this sweep
   int32_t *log;      // G x CLDIAM_STAGE_LOG x 4
   uint64_t *key;
   uint64_t *R;
@@ -150,6 +151,7 @@ struct Job {
   int32_t *C;
   int32_t G;
   int32_t local_rounds;   // local relaxation rounds per RELAX run
+  int32_t nblocks;        // workgroups of a sweep launch
 };
 
 constexpr int kThreads = 1024;
@@ -161,6 +163,7 @@ constexpr int kMidCap = 2048;     // deferred wave rows per round
 constexpr int kBigCap = 128;      // deferred workgroup rows per round
 constexpr int kLocalRounds = 4;   // default local relaxation rounds per RELAX run
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
+constexpr uint32_t kPassChunk = kThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
 
 // ------------------------------------------------------------- control --
 
@@ -302,8 +305,21 @@ __device__ void control_block(const Job &job) {
     if (g < job.G) {
       if (ctl->error == 0 || job.st[g].phase == PH_DONE) control_graph(job, g, sweep_id);
       if (ctl->error != 0 && job.st[g].phase != PH_DONE) job.st[g].phase = PH_DONE;
-      items = items_of(job.st[g], job.cn[g]);
-      if (job.st[g].phase != PH_DONE && job.st[g].phase != PH_IDLE) atomicAnd(&alldone, 0u);
+      const uint32_t phase = job.st[g].phase;
+      const uint32_t n_items = items_of(job.st[g], job.cn[g]);
+      // Every graph is cut into its own chunks, at most one per workgroup, so
+      // that the frontier of each graph is spread over the whole grid whatever
+      // the other graphs of the job are doing (a node pass of millions of
+      // cheap items beside a small frontier of costly rows).
+      uint32_t per = 0;
+      if (n_items) {
+        per = (n_items + (uint32_t)job.nblocks - 1) / (uint32_t)job.nblocks;
+        if (phase != PH_RELAX && phase != PH_NEXT && per < kPassChunk) per = kPassChunk;
+        items = (n_items + per - 1) / per;
+      }
+      job.seg[job.G + 1 + g] = per;
+      job.seg[2 * job.G + 1 + g] = n_items;
+      if (phase != PH_DONE && phase != PH_IDLE) atomicAnd(&alldone, 0u);
     }
     scan[threadIdx.x] = items;
     __syncthreads();
@@ -601,7 +617,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   const GState &s = job.st[g];
   GCount &cn = job.cn[g];
   const int64_t off = d.off;
-  const uint32_t phase = s.phase, base_idx = job.seg[g];
+  const uint32_t phase = s.phase;
   const uint32_t delta = s.delta, level_id = s.level_id, stage = s.stage, ucur = s.ucur;
   const uint32_t fcur = s.fcur, fnxt = s.fnxt, blk = s.blk;
   const uint64_t T = s.T;
@@ -639,7 +655,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   for (uint32_t r = a; r < b; r += blockDim.x) {
     const uint32_t i = r + threadIdx.x;
     if (i < b) {
-      const uint32_t idx = i - base_idx;
+      const uint32_t idx = i;
       switch (phase) {
         case PH_SELECT: {
           const int32_t v = job.U[ucur][off + idx];
@@ -739,7 +755,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   return scanned;
 }
 
-// Item index -> graph (largest g with seg[g] <= i).
+// Chunk index -> graph (largest g with seg[g] <= i).
 __device__ __forceinline__ int graph_of(const Job &job, uint32_t i) {
   int lo = 0, hi = job.G - 1;
   while (lo < hi) {
@@ -749,23 +765,23 @@ __device__ __forceinline__ int graph_of(const Job &job, uint32_t i) {
   return lo;
 }
 
-// Each workgroup takes one contiguous range of the sweep's index space and
-// walks it graph by graph.
+// The sweep's work is a list of chunks, each a range of one graph's items
+// (at most one chunk of a graph per workgroup); workgroup b takes chunks b,
+// b + nblocks, ...
 __device__ void sweep(const Job &job, uint32_t block, uint32_t nblocks, Stage &S) {
   const uint32_t total = job.ctl->total;
   const uint32_t it = job.ctl->sweep_id;
-  const uint32_t per = (total + nblocks - 1) / nblocks;
-  const uint32_t lo = block * per;
-  const uint32_t hi = lo + per < total ? lo + per : total;
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) S.flush = 0;
   __syncthreads();
   uint32_t scanned = 0;
-  for (uint32_t i = lo; i < hi;) {
-    const int g = graph_of(job, i);
-    const uint32_t end = job.seg[g + 1] < hi ? job.seg[g + 1] : hi;
-    scanned += process_run(job, g, i, end, it, S);
-    i = end;
+  for (uint32_t v = block; v < total; v += nblocks) {
+    const int g = graph_of(job, v);
+    const uint32_t per = job.seg[job.G + 1 + g];
+    const uint32_t n_items = job.seg[2 * job.G + 1 + g];
+    const uint32_t lo = (v - job.seg[g]) * per;
+    const uint32_t hi = lo + per < n_items ? lo + per : n_items;
+    scanned += process_run(job, g, lo, hi, it, S);
   }
   for (int o = 32; o >= 1; o >>= 1) scanned += __shfl_xor(scanned, o);
   if (cld_lane() == 0 && scanned) atomicAdd(&job.ctl->arcs.v, (unsigned long long)scanned);
@@ -841,7 +857,7 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto p_st = a.template take<GState>(G);
   auto p_cn = a.template take<GCount>(G);
   auto p_ctl = a.template take<Ctl>(1);
-  auto p_seg = a.template take<uint32_t>((size_t)G + 1);
+  auto p_seg = a.template take<uint32_t>(3 * (size_t)G + 1);
   auto p_log = a.template take<int32_t>((size_t)G * CLDIAM_STAGE_LOG * 4);
   auto p_key = a.template take<uint64_t>(N);
   auto p_R = a.template take<uint64_t>(N);
@@ -996,7 +1012,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     cld::set_error("decompose: workspace of %zu bytes, %zu needed", ws_bytes, cldiam_decompose_workspace_size(N, G));
     return CLDIAM_ENOMEM;
   }
-  Job job;
+  Job job{};
   job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
   job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
@@ -1033,6 +1049,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   const bool persistent = driver == CLDIAM_DRIVER_PERSISTENT && blocks > 0;
   if (!persistent && blocks <= 0) blocks = 256;
   if (blocks > 65535) blocks = 65535;
+  job.nblocks = blocks;
   Ctl *hc = host_ctl();
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1206,6 +1223,7 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   int rc = grid_blocks(CLDIAM_DRIVER_HOST, tuning ? tuning->grid_blocks : 0, &s->blocks);
   if (rc) { delete s; return rc; }
   if (s->blocks <= 0) s->blocks = 256;
+  job.nblocks = s->blocks;
   s->desc.assign(max_graphs, GDesc{});
   s->tag.assign(max_graphs, 0);
   s->active.assign(max_graphs, 0);

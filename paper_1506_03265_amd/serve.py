@@ -179,28 +179,60 @@ def percentile(xs, p: float) -> float:
 
 
 def serve_engine(requests, graphs: dict, max_graphs: int = 64, node_capacity: int = 0, sweeps_per_step: int = 4,
-                 workers: int = 4, keep_outputs: bool = False, time_scale: float = 1.0, local_rounds: int = -1):
-    """Continuous batching inside one device job: arrived requests are
-    submitted to a cldiam server (admitted between sweeps as slots and node
-    ranges free up, all admitted requests advancing together), finished
+                 workers: int = 4, keep_outputs: bool = False, time_scale: float = 1.0, local_rounds: int = -1,
+                 split_nodes: int = 0):
+    """Continuous batching inside device jobs: arrived requests are submitted
+    to a cldiam server (admitted between sweeps as slots and node ranges free
+    up, all admitted requests advancing in the same sweeps); finished
     decompositions go to `workers` threads that build the quotient and the
-    estimate on their own streams.  Returns (results sorted by request id,
-    wall seconds)."""
+    estimate on their own streams.  With split_nodes > 0 there are two
+    servers, each stepped by its own thread on its own stream: one for graphs
+    of fewer nodes than split_nodes and one for the rest, so that the long
+    sweeps of large graphs do not hold back small requests.  Returns (results
+    sorted by request id, wall seconds)."""
     import queue as _queue
 
     from . import Server
 
     torch = _torch()
     reqs = sorted(requests, key=lambda r: r.arrival_s)
-    if node_capacity <= 0:
-        node_capacity = max(sum(sorted((g.n for g in graphs.values()), reverse=True)[:8]),
-                            max(g.n for g in graphs.values()))
-    server = Server(node_capacity, max_graphs, local_rounds=local_rounds)
+    classes = [lambda n: True] if split_nodes <= 0 else [lambda n: n < split_nodes, lambda n: n >= split_nodes]
+    caps = []
+    for member in classes:
+        ns = sorted((g.n for g in graphs.values() if member(g.n)), reverse=True)
+        caps.append(node_capacity if node_capacity > 0 else max(sum(ns[:8]), ns[0] if ns else 1, 1))
+    servers = [Server(c, max_graphs, local_rounds=local_rounds) for c in caps]
+    inboxes = [_queue.Queue() for _ in servers]
     work = _queue.Queue()
     results, errors = [], []
     lock = threading.Lock()
     by_id = {r.rid: r for r in reqs}
     t_start = time.perf_counter()
+
+    def stepper(srv, inbox):
+        closed = False
+        try:
+            while True:
+                while True:
+                    try:
+                        item = inbox.get(block=not srv.outputs and not closed, timeout=0.05)
+                    except _queue.Empty:
+                        break
+                    if item is None:
+                        closed = True
+                        break
+                    g, tau, seed, rid = item
+                    srv.submit(g, tau, seed, rid)
+                if srv.outputs:
+                    srv.step(sweeps_per_step)
+                    t_dec = time.perf_counter()
+                    for tag, st, g, cluster, D in srv.poll():
+                        work.put((tag, st, g, cluster, D, t_dec))
+                elif closed:
+                    return
+        except BaseException as e:
+            with lock:
+                errors.append(e)
 
     def worker():
         stream = torch.cuda.Stream()
@@ -233,8 +265,9 @@ def serve_engine(requests, graphs: dict, max_graphs: int = 64, node_capacity: in
                 with lock:
                     errors.append(e)
 
+    steppers = [threading.Thread(target=stepper, args=(srv, box), daemon=True) for srv, box in zip(servers, inboxes)]
     threads = [threading.Thread(target=worker, daemon=True) for _ in range(workers)]
-    for th in threads:
+    for th in steppers + threads:
         th.start()
     i, n_total = 0, len(reqs)
     try:
@@ -242,28 +275,30 @@ def serve_engine(requests, graphs: dict, max_graphs: int = 64, node_capacity: in
             now = time.perf_counter() - t_start
             while i < n_total and reqs[i].arrival_s * time_scale <= now:
                 r = reqs[i]
-                server.submit(graphs[r.graph], r.tau, r.seed, r.rid)
+                g = graphs[r.graph]
+                k = 0 if len(classes) == 1 or classes[0](g.n) else 1
+                inboxes[k].put((g, r.tau, r.seed, r.rid))
                 i += 1
-            if server.outputs:   # submitted and not yet polled
-                active, queued = server.step(sweeps_per_step)
-                t_dec = time.perf_counter()
-                for tag, st, g, cluster, D in server.poll():
-                    work.put((tag, st, g, cluster, D, t_dec))
             with lock:
                 finished = len(results) + len(errors)
-            if finished >= n_total or errors:
+                failed = bool(errors)
+            if finished >= n_total or failed:
                 break
-            if not server.outputs:
-                if i < n_total:
-                    time.sleep(max(0.0, min(0.002, reqs[i].arrival_s * time_scale - (time.perf_counter() - t_start))))
-                else:
-                    time.sleep(0.0005)
+            wait = 0.0005
+            if i < n_total:
+                wait = max(0.0, min(0.002, reqs[i].arrival_s * time_scale - (time.perf_counter() - t_start)))
+            time.sleep(wait)
     finally:
+        for box in inboxes:
+            box.put(None)
+        for th in steppers:
+            th.join()
         for _ in threads:
             work.put(None)
         for th in threads:
             th.join()
-        server.close()
+        for srv in servers:
+            srv.close()
     wall = time.perf_counter() - t_start
     if errors:
         raise errors[0]

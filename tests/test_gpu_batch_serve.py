@@ -183,9 +183,11 @@ def test_engine_serving_equals_alone_results():
             for i, t in enumerate(np.cumsum(rng.exponential(0.001, size=30)))]
     _say("[systems] engine serving of 30 requests")
     eng, _ = serve.serve_engine(reqs, pool, max_graphs=8, keep_outputs=True)
+    split, _ = serve.serve_engine(reqs, pool, max_graphs=4, keep_outputs=True, split_nodes=20000)
     alone, _ = serve.serve(reqs, pool, workers=1, keep_outputs=True)
-    assert [r.rid for r in eng] == list(range(30))
-    for a, b in zip(eng, alone):
+    assert [r.rid for r in eng] == [r.rid for r in split] == list(range(30))
+    for a, b, c in zip(eng, alone, split):
+        assert bool((c.cluster == b.cluster).all()) and bool((c.D == b.D).all()) and c.phi_approx == b.phi_approx
         assert a.status == 0
         assert bool((a.cluster == b.cluster).all()) and bool((a.D == b.D).all())
         assert (a.num_clusters, a.radius, a.phi_gc, a.phi_approx) == (b.num_clusters, b.radius, b.phi_gc, b.phi_approx)
