@@ -43,6 +43,10 @@ class _Stats(ctypes.Structure):
                 ("sum_arcs", ctypes.c_uint64), ("sum_covered", ctypes.c_uint64)]
 
 
+class _StepStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("messages", ctypes.c_uint64), ("updates", ctypes.c_uint64)]
+
+
 class _Log(ctypes.Structure):
     _fields_ = [("uncovered", ctypes.POINTER(ctypes.c_int32)), ("centers", ctypes.POINTER(ctypes.c_int32)),
                 ("covered", ctypes.POINTER(ctypes.c_int32)), ("delta", ctypes.POINTER(ctypes.c_uint32)),
@@ -62,6 +66,9 @@ def _load():
         lib.or_default_delta.restype = ctypes.c_uint32
         lib.or_decompose.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.c_uint64, i32p, u64p, P(_Stats), P(_Log)]
+        lib.or_decompose_steps.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_uint32, i32p, u64p, P(_Stats), P(_StepStats),
+                                           P(_Log)]
         lib.or_quotient.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, u64p, i32p, P(i32p),
                                     P(ctypes.c_int64), P(i32p), P(i32p), P(u64p), P(ctypes.c_int64)]
         lib.or_free.argtypes = [ctypes.c_void_p]
@@ -144,6 +151,39 @@ def decompose(g, tau: int, seed: int, delta0: int = 0, log_cap: int = 256) -> De
     s = min(st.stages, log_cap)
     work = dict(sum_uncovered=int(st.sum_uncovered), sum_acting=int(st.sum_acting),
                 sum_arcs=int(st.sum_arcs), sum_covered=int(st.sum_covered))
+    return Decomposition(cluster, D, st.stages, st.levels, st.delta0, st.delta_end, st.stop, st.num_clusters,
+                         st.singletons, int(st.radius), lu[:s].tolist(), lc[:s].tolist(), lv[:s].tolist(),
+                         ld[:s].tolist(), work)
+
+
+def decompose_steps(g, tau: int, seed: int, delta0: int = 0, step_cap: int = 0,
+                    log_cap: int = 256) -> Decomposition:
+    """CLUSTER(G, tau) with the literal PartialGrowth of Algorithm 1:
+    synchronous Delta-growing steps, the strict-distance tie rule, the
+    per-step half-coverage stop, Delta doubled one step at a time, and an
+    optional cap on the steps of one PartialGrowth call (step_cap, 0 = none).
+    work also holds rounds, messages and updates (see cldiam_oracle.c)."""
+    rp, col, w = _csr_args(g)
+    n = g.n
+    cluster = np.empty(n, dtype=np.int32)
+    D = np.empty(n, dtype=np.uint64)
+    st = _Stats()
+    ss = _StepStats()
+    lu = np.zeros(log_cap, np.int32)
+    lc = np.zeros(log_cap, np.int32)
+    lv = np.zeros(log_cap, np.int32)
+    ld = np.zeros(log_cap, np.uint32)
+    lg = _Log(_p(lu, ctypes.c_int32), _p(lc, ctypes.c_int32), _p(lv, ctypes.c_int32), _p(ld, ctypes.c_uint32),
+              log_cap)
+    rc = _load().or_decompose_steps(n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
+                                    tau, delta0, seed, step_cap, _p(cluster, ctypes.c_int32),
+                                    _p(D, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(ss), ctypes.byref(lg))
+    if rc != OR_OK:
+        raise OracleError(rc, "or_decompose_steps")
+    s = min(st.stages, log_cap)
+    work = dict(sum_uncovered=int(st.sum_uncovered), sum_acting=int(st.sum_acting),
+                sum_arcs=int(st.sum_arcs), sum_covered=int(st.sum_covered), rounds=int(ss.rounds),
+                messages=int(ss.messages), updates=int(ss.updates))
     return Decomposition(cluster, D, st.stages, st.levels, st.delta0, st.delta_end, st.stop, st.num_clusters,
                          st.singletons, int(st.radius), lu[:s].tolist(), lc[:s].tolist(), lv[:s].tolist(),
                          ld[:s].tolist(), work)

@@ -188,6 +188,130 @@ def cluster(n, edges, tau, seed, delta0=0, mode="apsp"):
                 radius=max(D) if D else 0, levels=levels)
 
 
+def partial_growth_steps(nodes, adj, delta, state, U, covered0, step_cap=0):
+    """Procedure PartialGrowth of Algorithm 1 taken literally: synchronous
+    Delta-growing steps (every node u with d_u < Delta offers d_u + w to each
+    neighbour over an edge with d_u + w <= Delta; v accepts only a strictly
+    smaller distance, the smallest center winning among the offers of one
+    step), repeated until a step updates no state or at least half of the
+    uncovered nodes U have d <= Delta, or after step_cap steps (0 = no cap).
+
+    Returns (steps executed, node updates, number of U nodes with d <= Delta,
+    whether the last step updated some state)."""
+    Uset = set(U)
+    covered = covered0
+    steps = updates = 0
+    if 2 * covered >= len(U):
+        return steps, updates, covered, False
+    while True:
+        offers = {}
+        for u in nodes:
+            du, cu = state[u]
+            if du >= delta:
+                continue
+            for v, w in adj[u].items():
+                if du + w > delta:
+                    continue
+                cand = (du + w, cu)
+                if cand[0] < state[v][0] and (v not in offers or cand < offers[v]):
+                    offers[v] = cand
+        steps += 1
+        for v, cand in offers.items():
+            if state[v][0] == INF and v in Uset:
+                covered += 1
+            state[v] = cand
+        updates += len(offers)
+        if not offers or 2 * covered >= len(U) or (step_cap and steps >= step_cap):
+            return steps, updates, covered, bool(offers)
+
+
+def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
+    """CLUSTER(G, tau) of Algorithm 1 with literal PartialGrowth (synchronous
+    steps, the strict-distance tie rule, the per-step half-coverage stop with
+    threshold |V_i - C_i| / 2, an optional cap on the steps of one
+    PartialGrowth call) and Delta doubled one step at a time; explicit
+    Contract after every stage.  A stage stops doubling when no uncovered
+    node is reachable from the clusters at any Delta.
+
+    Returns dict(cluster, D, stages, delta_end, num_clusters, radius, levels,
+    rounds, updates)."""
+    gamma = 4.0 * math.log(2.0)
+    L = math.log2(n)
+    stop = math.ceil(8.0 * tau * L)
+    m_arcs = 2 * len(edges)
+    if delta0:
+        delta = delta0
+    else:
+        delta = max(1, (2 * sum(w for _, _, w in edges)) // m_arcs) if m_arcs else 1
+    k0, k1 = seed & M32, (seed >> 32) & M32
+    Vi = set(range(n))
+    adj = {v: {} for v in range(n)}
+    for u, v, w in edges:
+        _add_edge(adj, u, v, w)
+    Ci = set()
+    cluster_of = [None] * n
+    D = [0] * n
+    R = [0] * n
+    s = levels = rounds = updates = 0
+    while True:
+        U = sorted(Vi - Ci)
+        if n < 2 or not U or len(U) < stop:
+            break
+        p = gamma * tau * L / len(U)
+        T = (1 << 32) if p >= 1.0 else math.floor(p * 4294967296.0)
+        new = [v for v in U if philox4x32_10((v, s, 0, 0), (k0, k1))[0] < T]
+        X = Ci | set(new)
+        state = {v: ((0, v) if v in X else (INF, None)) for v in Vi}
+        nodes = sorted(Vi)
+        covered = len(new)
+        while 2 * covered < len(U):
+            levels += 1
+            k, up, covered, moved = partial_growth_steps(nodes, adj, delta, state, U, covered, step_cap)
+            rounds += k
+            updates += up
+            if 2 * covered >= len(U):
+                break
+            reach = {v for v in Vi if state[v][0] != INF}
+            if not moved and not any(v not in reach for u in reach for v in adj[u]):
+                break
+            if 2 * delta > (1 << 31):
+                raise OverflowError("Delta above 2^31")
+            delta *= 2
+        got = [v for v in U if state[v][0] <= delta]
+        for v in got:
+            c = state[v][1]
+            cluster_of[v] = c
+            D[v] = state[v][0] + R[c]
+        for v in got:
+            R[cluster_of[v]] = max(R[cluster_of[v]], D[v])
+        clustered = set(X) | set(got)
+        label = {v: (v if v in X else state[v][1]) for v in clustered}
+        nadj = {v: {} for v in Vi if v not in clustered or v in X}
+        for u in Vi:
+            for v, w in adj[u].items():
+                if u > v:
+                    continue
+                cu, cv = label.get(u), label.get(v)
+                if cu is not None and cv is not None:
+                    continue
+                if cu is None and cv is None:
+                    _add_edge(nadj, u, v, w)
+                elif cu is not None:
+                    _add_edge(nadj, cu, v, w)
+                else:
+                    _add_edge(nadj, u, cv, w)
+        Vi = set(nadj.keys())
+        adj = nadj
+        Ci = X
+        s += 1
+    for v in Vi - Ci:
+        cluster_of[v] = v
+        D[v] = 0
+    return dict(cluster=cluster_of, D=D, stages=s, delta_end=delta,
+                num_clusters=sum(1 for v in range(n) if cluster_of[v] == v),
+                radius=max(D) if D else 0, levels=levels, rounds=rounds, updates=updates)
+
+
 def quotient(n, edges, cluster_of, D):
     """Weighted quotient graph of Section 4 as a dict (a, b) -> weight over
     dense cluster indices a < b (clusters numbered by ascending center)."""

@@ -281,6 +281,227 @@ done:
   return rc;
 }
 
+/* ------------------------------------ decomposition, literal growth steps -- */
+
+/*
+ * CLUSTER(G, tau) with Procedure PartialGrowth of Algorithm 1 taken
+ * literally: each Delta-growing step is synchronous (all offers of a step are
+ * computed from the state before the step), a node accepts an offer only if
+ * its distance is strictly smaller than the node's current one (among the
+ * offers of one step, the smallest distance and then the smallest center
+ * wins), and PartialGrowth stops as soon as a step updates no state or at
+ * least half of the stage's uncovered nodes are covered (threshold
+ * |V_i - C_i| / 2, the outer loop's), or after step_cap steps (0 = no cap).
+ * The outer loop doubles Delta one step at a time while fewer than half are
+ * covered; a stage whose growth has stopped with no node reachable at any
+ * Delta keeps what it covered.  If the new centers alone cover half, the
+ * stage performs no step.
+ *
+ * Counters (the paper's experiments report rounds and work):
+ *   rounds   = growing steps executed (including a final step that updates
+ *              nothing);
+ *   updates  = node states changed, summed over steps;
+ *   messages = offers sent, summed over steps: in a step, each node of the
+ *              active set sends one offer over every arc with d_u + w <=
+ *              Delta.  The active set of a step is the set of nodes updated
+ *              by the previous step; in the first step of a stage it is the
+ *              new centers plus the previous stage's carried sources; in the
+ *              first step after Delta doubles it is the nodes still active plus
+ *              every node that, at a step of the previous Delta, had an arc
+ *              with d_u + w > Delta.  The carried sources of a stage are the
+ *              nodes still active when its growth stopped plus the nodes found
+ *              with such an arc at the last Delta.  Nodes assigned in earlier
+ *              stages send at distance 0 with their cluster's label (Contract).
+ */
+typedef struct {
+  uint64_t rounds;
+  uint64_t messages;
+  uint64_t updates;
+} or_step_stats;
+
+int or_decompose_steps(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                       uint32_t tau, uint32_t delta0, uint64_t seed, uint32_t step_cap,
+                       int32_t *cluster, uint64_t *D, or_stats *st, or_step_stats *ss, or_stage_log *lg) {
+  if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st || !ss) return OR_EINVAL;
+  memset(st, 0, sizeof *st);
+  memset(ss, 0, sizeof *ss);
+  int64_t m = row_ptr[n];
+  uint64_t delta = delta0 ? delta0 : or_default_delta(m, w);
+  st->delta0 = (uint32_t)delta;
+  if (delta > DELTA_MAX) return OR_EOVERFLOW;
+  const double gamma = 4.0 * M_LN2;
+  const double L = log2((double)n);
+  const int64_t stop = (int64_t)ceil(8.0 * tau * L);
+  st->stop = (int32_t)stop;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+
+  const uint64_t UNSET = INF64;
+  int32_t *U = malloc((size_t)n * 4);
+  uint64_t *dist = malloc((size_t)n * 8);      /* stage-local d (UNSET = infinity) */
+  uint32_t *lab = malloc((size_t)n * 4);       /* c */
+  uint64_t *R = calloc((size_t)n, 8);
+  int32_t *act = malloc((size_t)n * 4), *nxt = malloc((size_t)n * 4), *blk = malloc((size_t)n * 4);
+  int64_t *amark = malloc((size_t)n * 8);      /* membership stamps of the three sets */
+  int64_t *nmark = malloc((size_t)n * 8);
+  int64_t *bmark = malloc((size_t)n * 8);
+  uint64_t *bd = malloc((size_t)n * 8);        /* best offer of the current step */
+  uint32_t *bl = malloc((size_t)n * 4);
+  int rc = OR_OK;
+  if (!U || !dist || !lab || !R || !act || !nxt || !blk || !amark || !nmark || !bmark || !bd || !bl) {
+    rc = OR_ENOMEM;
+    goto done;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    U[v] = v; cluster[v] = -1; D[v] = 0; dist[v] = UNSET; lab[v] = 0;
+    amark[v] = nmark[v] = bmark[v] = -1;
+  }
+  int64_t nU = n, nact = 0, nblk = 0;
+  int64_t stamp = 0;       /* increases for every new set */
+  int64_t aset = ++stamp;  /* stamp of the active set */
+  int64_t bset = ++stamp;  /* stamp of the set of nodes with an arc beyond Delta */
+  int32_t s = 0;
+
+  while (n > 1 && nU > 0 && nU >= stop) {
+    if (s >= MAX_STAGES) { rc = OR_ESTAGES; goto done; }
+    double p = gamma * tau * L / (double)nU;
+    uint64_t T = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0);
+    int64_t covered = 0;
+    int32_t ncent = 0;
+    /* carried sources stay in the active set; the new centers join it */
+    for (int64_t i = 0; i < nU; ++i) {
+      uint32_t v = (uint32_t)U[i];
+      uint32_t c[4] = {v, (uint32_t)s, 0, 0};
+      philox4x32_10(c, k0, k1);
+      if ((uint64_t)c[0] < T) {
+        dist[v] = 0;
+        lab[v] = v;
+        ncent++;
+        covered++;
+        if (amark[v] != aset) { amark[v] = aset; act[nact++] = (int32_t)v; }
+      }
+    }
+    while (2 * covered < nU) {
+      st->levels++;
+      uint32_t steps = 0;
+      int moved = 0;
+      /* PartialGrowth(G_i, Delta) */
+      for (;;) {
+        ss->rounds++;
+        steps++;
+        st->sum_acting += (uint64_t)nact;
+        int64_t nset = ++stamp, nn = 0;
+        for (int64_t i = 0; i < nact; ++i) {
+          int32_t u = act[i];
+          uint64_t du = dist[u];
+          int heavy = 0;
+          for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+            uint64_t cand = du + w[a];
+            if (cand > delta) { heavy = 1; continue; }
+            ss->messages++;
+            st->sum_arcs++;
+            int32_t v = col[a];
+            if (cand >= dist[v]) continue;        /* only a strictly smaller distance */
+            if (nmark[v] != nset) {
+              nmark[v] = nset;
+              nxt[nn++] = v;
+              bd[v] = cand;
+              bl[v] = lab[u];
+            } else if (cand < bd[v] || (cand == bd[v] && lab[u] < bl[v])) {
+              bd[v] = cand;
+              bl[v] = lab[u];
+            }
+          }
+          if (heavy && bmark[u] != bset) { bmark[u] = bset; blk[nblk++] = u; }
+        }
+        for (int64_t i = 0; i < nn; ++i) {
+          int32_t v = nxt[i];
+          if (dist[v] == UNSET) covered++;
+          dist[v] = bd[v];
+          lab[v] = bl[v];
+        }
+        ss->updates += (uint64_t)nn;
+        /* the updated nodes are the next active set */
+        aset = ++stamp;
+        for (int64_t i = 0; i < nn; ++i) { act[i] = nxt[i]; amark[act[i]] = aset; }
+        nact = nn;
+        moved = nn > 0;
+        if (!moved || 2 * covered >= nU || (step_cap && steps >= step_cap)) break;
+      }
+      if (2 * covered >= nU) break;
+      if (!moved) {
+        /* fixpoint at this Delta: is any uncovered node reachable at all? */
+        int reach = 0;
+        for (int64_t i = 0; i < nblk && !reach; ++i) {
+          int32_t u = blk[i];
+          for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
+            if (dist[col[a]] == UNSET) { reach = 1; break; }
+        }
+        if (!reach) break;
+      }
+      if (2 * delta > DELTA_MAX) { rc = OR_EOVERFLOW; goto done; }
+      delta *= 2;
+      /* the next PartialGrowth starts from the active nodes and every node
+       * that had an arc beyond the old Delta */
+      for (int64_t i = 0; i < nblk; ++i) {
+        int32_t u = blk[i];
+        if (amark[u] != aset) { amark[u] = aset; act[nact++] = u; }
+      }
+      bset = ++stamp;
+      nblk = 0;
+    }
+    /* assign the covered nodes of U */
+    int32_t nnew = 0;
+    for (int64_t i = 0; i < nU; ++i) {
+      int32_t v = U[i];
+      if (dist[v] == UNSET) continue;
+      cluster[v] = (int32_t)lab[v];
+      D[v] = dist[v] + R[lab[v]];
+      nnew++;
+    }
+    for (int64_t i = 0; i < nU; ++i) {
+      int32_t v = U[i];
+      if (cluster[v] >= 0 && D[v] > R[cluster[v]]) R[cluster[v]] = D[v];
+    }
+    if (lg && s < lg->cap) {
+      if (lg->uncovered) lg->uncovered[s] = (int32_t)nU;
+      if (lg->centers) lg->centers[s] = ncent;
+      if (lg->covered) lg->covered[s] = nnew;
+      if (lg->delta) lg->delta[s] = (uint32_t)delta;
+    }
+    st->sum_uncovered += (uint64_t)nU;
+    st->sum_covered += (uint64_t)nnew;
+    /* Contract: assigned nodes become distance-0 sources with their label */
+    for (int64_t i = 0; i < nU; ++i) {
+      int32_t v = U[i];
+      if (cluster[v] >= 0) { dist[v] = 0; lab[v] = (uint32_t)cluster[v]; }
+    }
+    /* carried sources: the active set plus the nodes with an arc beyond Delta */
+    for (int64_t i = 0; i < nblk; ++i) {
+      int32_t u = blk[i];
+      if (amark[u] != aset) { amark[u] = aset; act[nact++] = u; }
+    }
+    bset = ++stamp;
+    nblk = 0;
+    int64_t k = 0;
+    for (int64_t i = 0; i < nU; ++i)
+      if (cluster[U[i]] < 0) U[k++] = U[i];
+    nU = k;
+    s++;
+  }
+  for (int64_t i = 0; i < nU; ++i) { cluster[U[i]] = U[i]; D[U[i]] = 0; }
+  st->singletons = (int32_t)nU;
+  st->stages = s;
+  st->delta_end = (uint32_t)delta;
+  for (int32_t v = 0; v < n; ++v) {
+    if (cluster[v] == v) st->num_clusters++;
+    if (D[v] > st->radius) st->radius = D[v];
+  }
+done:
+  free(U); free(dist); free(lab); free(R); free(act); free(nxt); free(blk);
+  free(amark); free(nmark); free(bmark); free(bd); free(bl);
+  return rc;
+}
+
 /* ------------------------------------------------------------ quotient -- */
 
 typedef struct { uint64_t key; uint64_t w; } qrec_t;
