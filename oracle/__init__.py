@@ -69,6 +69,8 @@ def _load():
         lib.or_decompose_steps.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint64, ctypes.c_uint32, i32p, u64p, P(_Stats), P(_StepStats),
                                            P(_Log)]
+        lib.or_decompose_cluster2.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.c_uint64, i32p, u64p, P(_Stats), u64p, P(_Log)]
         lib.or_quotient.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, u64p, i32p, P(i32p),
                                     P(ctypes.c_int64), P(i32p), P(i32p), P(u64p), P(ctypes.c_int64)]
         lib.or_free.argtypes = [ctypes.c_void_p]
@@ -184,6 +186,35 @@ def decompose_steps(g, tau: int, seed: int, delta0: int = 0, step_cap: int = 0,
     work = dict(sum_uncovered=int(st.sum_uncovered), sum_acting=int(st.sum_acting),
                 sum_arcs=int(st.sum_arcs), sum_covered=int(st.sum_covered), rounds=int(ss.rounds),
                 messages=int(ss.messages), updates=int(ss.updates))
+    return Decomposition(cluster, D, st.stages, st.levels, st.delta0, st.delta_end, st.stop, st.num_clusters,
+                         st.singletons, int(st.radius), lu[:s].tolist(), lc[:s].tolist(), lv[:s].tolist(),
+                         ld[:s].tolist(), work)
+
+
+def decompose_cluster2(g, tau: int, seed: int, delta0: int = 0, log_cap: int = 256) -> Decomposition:
+    """CLUSTER2(G, tau) of Algorithm 2 (Section 4) with the readings stated in
+    cldiam_oracle.c.  work['radius1'] is R_CL, the radius of the preliminary
+    CLUSTER(G, tau) run; delta_end is 2 R_CL."""
+    rp, col, w = _csr_args(g)
+    n = g.n
+    cluster = np.empty(n, dtype=np.int32)
+    D = np.empty(n, dtype=np.uint64)
+    st = _Stats()
+    r1 = ctypes.c_uint64()
+    lu = np.zeros(log_cap, np.int32)
+    lc = np.zeros(log_cap, np.int32)
+    lv = np.zeros(log_cap, np.int32)
+    ld = np.zeros(log_cap, np.uint32)
+    lg = _Log(_p(lu, ctypes.c_int32), _p(lc, ctypes.c_int32), _p(lv, ctypes.c_int32), _p(ld, ctypes.c_uint32),
+              log_cap)
+    rc = _load().or_decompose_cluster2(n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32),
+                                       _p(w, ctypes.c_uint32), tau, delta0, seed, _p(cluster, ctypes.c_int32),
+                                       _p(D, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(r1),
+                                       ctypes.byref(lg))
+    if rc != OR_OK:
+        raise OracleError(rc, "or_decompose_cluster2")
+    s = min(st.stages, log_cap)
+    work = dict(sum_uncovered=int(st.sum_uncovered), sum_covered=int(st.sum_covered), radius1=int(r1.value))
     return Decomposition(cluster, D, st.stages, st.levels, st.delta0, st.delta_end, st.stop, st.num_clusters,
                          st.singletons, int(st.radius), lu[:s].tolist(), lc[:s].tolist(), lv[:s].tolist(),
                          ld[:s].tolist(), work)

@@ -312,6 +312,92 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
                 radius=max(D) if D else 0, levels=levels, rounds=rounds, updates=updates)
 
 
+def cluster2(n, edges, tau, seed, delta0=0):
+    """CLUSTER2(G, tau) of Algorithm 2 with an explicit Contract2 after every
+    iteration.  R_CL is the radius of cluster(..., mode="apsp"); every growth
+    runs to its fixpoint with Delta2 = 2 R_CL, each node's state being the
+    lexicographic minimum over X of (dist, x) where dist uses only edges of
+    weight <= Delta2 and is at most Delta2 (Floyd-Warshall on G_i).  Contract2
+    removes the grown nodes, keeps their centers, and replaces every edge
+    (u, v) of weight <= Delta2 with c_u defined and c_v undefined by (c_u, v)
+    of weight d_u + w - Delta2.  D of a node reached in iteration i by the
+    cluster of a center drawn in iteration j is its G_i distance plus
+    Delta2 (i - j).
+
+    Returns dict(cluster, D, iterations, delta2, radius1, num_clusters,
+    radius)."""
+    r1 = cluster(n, edges, tau, seed, delta0=delta0, mode="apsp")["radius"]
+    d2 = 2 * int(r1)
+    if d2 > (1 << 31):
+        raise OverflowError("2 R_CL above 2^31")
+    k0, k1 = seed & M32, (seed >> 32) & M32
+    iters = 0
+    while (1 << iters) < n:
+        iters += 1
+    Vi = set(range(n))
+    adj = {v: {} for v in range(n)}
+    for u, v, w in edges:
+        if w <= d2:
+            _add_edge(adj, u, v, w)
+    Ci = set()
+    birth = {}
+    cluster_of = [None] * n
+    D = [0] * n
+    for i in range(1, iters + 1):
+        U = sorted(Vi - Ci)
+        p = 2.0 ** i / n
+        T = (1 << 32) if p >= 1.0 else math.floor(p * 4294967296.0)
+        new = [v for v in U if philox4x32_10((v, i, 0, 1), (k0, k1))[0] < T]
+        for v in new:
+            birth[v] = i
+        X = Ci | set(new)
+        nodes = sorted(Vi)
+        idx, dist = floyd_warshall(nodes, adj)
+        state = {}
+        for v in U:
+            best = (INF, None)
+            for x in X:
+                dxv = dist[idx[x], idx[v]]
+                if dxv <= d2 and (dxv, x) < best:
+                    best = (dxv, x)
+            state[v] = (0, v) if v in new else best
+        got = [v for v in U if state[v][1] is not None]
+        for v in got:
+            d, c = state[v]
+            cluster_of[v] = c
+            D[v] = int(d) + d2 * (i - birth[c])
+        # Procedure Contract2
+        label = {v: state[v][1] for v in got}
+        for x in Ci:
+            label[x] = x
+        nadj = {v: {} for v in Vi if v not in label or v in X}
+        for u in Vi:
+            for v, w in adj[u].items():
+                if u > v:
+                    continue
+                cu, cv = label.get(u), label.get(v)
+                if cu is not None and cv is not None:
+                    continue
+                if cu is None and cv is None:
+                    _add_edge(nadj, u, v, w)
+                    continue
+                # the endpoint in a cluster (a) and the one outside it (b)
+                a, b, ca = (u, v, cu) if cu is not None else (v, u, cv)
+                da = 0 if a in Ci else int(state[a][0])
+                nw = da + w - d2
+                assert 1 <= nw <= d2
+                _add_edge(nadj, ca, b, nw)
+        Vi = set(nadj.keys())
+        adj = nadj
+        Ci = X
+    for v in range(n):
+        if cluster_of[v] is None:
+            cluster_of[v] = v
+            D[v] = 0
+    return dict(cluster=cluster_of, D=D, iterations=iters, delta2=d2, radius1=int(r1),
+                num_clusters=sum(1 for v in range(n) if cluster_of[v] == v), radius=max(D) if D else 0)
+
+
 def quotient(n, edges, cluster_of, D):
     """Weighted quotient graph of Section 4 as a dict (a, b) -> weight over
     dense cluster indices a < b (clusters numbered by ascending center)."""

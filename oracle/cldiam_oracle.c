@@ -502,6 +502,136 @@ done:
   return rc;
 }
 
+/* ------------------------------------------------ decomposition, CLUSTER2 -- */
+
+/*
+ * CLUSTER2(G, tau) of Algorithm 2 (Section 4).  R_CL is the radius bound
+ * max D of CLUSTER(G, tau) above (same tau, seed and initial Delta); every
+ * growth uses Delta2 = 2 R_CL.  Iterations i = 1 .. ceil(log2 n): each
+ * uncovered node becomes a new center with probability 2^i / n (word 0 of
+ * Philox4x32-10(counter (v, i, 0, 1), key seed) below floor(p 2^32), 2^32
+ * once p >= 1, so the last iteration takes every uncovered node); then all
+ * clusters grow to the fixpoint of Delta2-growing steps (PartialGrowth2,
+ * lexicographic (d, c) minimum as in CLUSTER).  Procedure Contract2 is
+ * implicit: a node u assigned in iteration i-1 at growth distance d_u offers
+ * its cluster's label at distance d_u + w - Delta2 to every unassigned
+ * neighbour over an edge with w <= Delta2 (such an edge has d_u + w > Delta2,
+ * or the neighbour would have been reached); that is the rescaled edge
+ * (c_u, v).  A node reached in iteration i by a cluster whose center was
+ * drawn in iteration j has D = d + Delta2 (i - j): the length of a path from
+ * the center, since each contraction shortens the paths behind it by exactly
+ * Delta2.  Delta2 above 2^31 is an overflow error.  Stats: stages =
+ * iterations, levels = iterations, delta0 = the CLUSTER run's, delta_end =
+ * Delta2, radius = max D; *radius1 = R_CL.
+ */
+int or_decompose_cluster2(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                          uint32_t tau, uint32_t delta0, uint64_t seed,
+                          int32_t *cluster, uint64_t *D, or_stats *st, uint64_t *radius1, or_stage_log *lg) {
+  if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st || !radius1) return OR_EINVAL;
+  or_stats st1;
+  int rc = or_decompose(n, row_ptr, col, w, tau, delta0, seed, cluster, D, &st1, NULL);
+  if (rc != OR_OK) return rc;
+  memset(st, 0, sizeof *st);
+  st->delta0 = st1.delta0;
+  st->stop = st1.stop;
+  *radius1 = st1.radius;
+  const uint64_t d2 = 2 * st1.radius;
+  if (d2 > DELTA_MAX) return OR_EOVERFLOW;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  int32_t iters = 0;
+  while (((int64_t)1 << iters) < (int64_t)n) iters++;   /* ceil(log2 n) */
+
+  int32_t *U = malloc((size_t)n * 4);
+  int32_t *settled = malloc((size_t)n * 4);
+  uint32_t *loc = malloc((size_t)n * 4);
+  uint32_t *lab = malloc((size_t)n * 4);
+  int32_t *birth = malloc((size_t)n * 4);
+  int32_t *prev = malloc((size_t)n * 4), *cur = malloc((size_t)n * 4);
+  heap_t h = {0};
+  if (!U || !settled || !loc || !lab || !birth || !prev || !cur) { rc = OR_ENOMEM; goto done; }
+  for (int32_t v = 0; v < n; ++v) { U[v] = v; cluster[v] = -1; D[v] = 0; settled[v] = 0; birth[v] = 0; }
+  int64_t nU = n, nprev = 0;
+  for (int32_t i = 1; i <= iters; ++i) {
+    const double p = ldexp(1.0, i) / (double)n;
+    const uint64_t T = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0);
+    h.len = 0;
+    int32_t ncent = 0;
+    for (int64_t k = 0; k < nU; ++k) {
+      uint32_t v = (uint32_t)U[k];
+      uint32_t c[4] = {v, (uint32_t)i, 0, 1};
+      philox4x32_10(c, k0, k1);
+      if ((uint64_t)c[0] < T) {
+        birth[v] = i;
+        if (heap_push(&h, 0, v, v)) { rc = OR_ENOMEM; goto done; }
+        ncent++;
+      }
+    }
+    /* Contract2's rescaled edges out of the clusters grown last iteration */
+    for (int64_t k = 0; k < nprev; ++k) {
+      int32_t u = prev[k];
+      for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+        int32_t v = col[a];
+        if (cluster[v] >= 0 || w[a] > d2) continue;
+        if (heap_push(&h, (uint64_t)loc[u] + w[a] - d2, (uint32_t)cluster[u], (uint32_t)v)) {
+          rc = OR_ENOMEM;
+          goto done;
+        }
+      }
+    }
+    /* PartialGrowth2 to the fixpoint: lexicographic Dijkstra within Delta2 */
+    int64_t ncur = 0;
+    while (h.len) {
+      item_t it = heap_pop(&h);
+      if (it.d > d2) break;
+      if (settled[it.v] == i) continue;
+      settled[it.v] = i;
+      loc[it.v] = (uint32_t)it.d;
+      lab[it.v] = it.c;
+      cur[ncur++] = (int32_t)it.v;
+      for (int32_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
+        int32_t x = col[a];
+        if (cluster[x] >= 0 || settled[x] == i) continue;
+        if (it.d + w[a] > d2) continue;
+        if (heap_push(&h, it.d + w[a], it.c, (uint32_t)x)) { rc = OR_ENOMEM; goto done; }
+      }
+    }
+    uint64_t covered = 0;
+    for (int64_t k = 0; k < ncur; ++k) {
+      int32_t v = cur[k];
+      cluster[v] = (int32_t)lab[v];
+      D[v] = (uint64_t)loc[v] + d2 * (uint64_t)(i - birth[lab[v]]);
+      covered++;
+    }
+    if (lg && i - 1 < lg->cap) {
+      if (lg->uncovered) lg->uncovered[i - 1] = (int32_t)nU;
+      if (lg->centers) lg->centers[i - 1] = ncent;
+      if (lg->covered) lg->covered[i - 1] = (int32_t)covered;
+      if (lg->delta) lg->delta[i - 1] = (uint32_t)d2;
+    }
+    st->sum_uncovered += (uint64_t)nU;
+    st->sum_covered += covered;
+    int32_t *t = prev; prev = cur; cur = t;
+    nprev = ncur;
+    int64_t k2 = 0;
+    for (int64_t k = 0; k < nU; ++k)
+      if (cluster[U[k]] < 0) U[k2++] = U[k];
+    nU = k2;
+  }
+  /* only for n = 1 (no iteration): the node is its own cluster */
+  for (int64_t k = 0; k < nU; ++k) { cluster[U[k]] = U[k]; D[U[k]] = 0; }
+  st->singletons = (int32_t)nU;
+  st->stages = iters;
+  st->levels = iters;
+  st->delta_end = (uint32_t)d2;
+  for (int32_t v = 0; v < n; ++v) {
+    if (cluster[v] == v) st->num_clusters++;
+    if (D[v] > st->radius) st->radius = D[v];
+  }
+done:
+  free(U); free(settled); free(loc); free(lab); free(birth); free(prev); free(cur); free(h.a);
+  return rc;
+}
+
 /* ------------------------------------------------------------ quotient -- */
 
 typedef struct { uint64_t key; uint64_t w; } qrec_t;
