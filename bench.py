@@ -28,6 +28,10 @@ Other workloads (each prints its own JSON line):
                       latency and requests/s
   --workload sssp     the Delta-stepping SSSP competitor on the road-like
                       mesh, best of several bucket widths
+  --workload variants CLUSTER, the literal step-synchronous variant and
+                      CLUSTER2 on the road-like mesh
+  --workload delta0   the initial-Delta experiment on a bimodal-weight mesh
+  --workload stepcap  the growing-step cap on skewed graphs
 
 Only one GPU is supported.
 """
@@ -69,7 +73,8 @@ def step_bench(args, name):
     log(f"[bench] ingest {ingest_ms:.1f} ms (H2D + validation + packing)")
 
     job = cd.DecomposeJob([dg], [(counts["tau"], counts["seed"], 0)], driver=args.driver,
-                          local_rounds=args.local_rounds, grid_blocks=args.grid_blocks)
+                          local_rounds=args.local_rounds, grid_blocks=args.grid_blocks,
+                          bucket_width=args.bucket_width)
     qjob = cd.QuotientJob(dg)
     ejob = cd.EstimateJob(1, 1, dev)   # grows to the quotient's size on first use
 
@@ -289,6 +294,140 @@ def serve_bench(args):
     }
 
 
+def _sssp_lower_bound(cd, dg, src, sweeps=4):
+    """Iterated SSSP: each sweep starts from the farthest node of the previous
+    one; the largest eccentricity found is a lower bound on the diameter."""
+    import torch
+    lb, s = 0, src
+    for _ in range(sweeps):
+        dist, mx = cd.cldiam_sssp_delta_stepping(dg, s, cd.default_bucket_delta(dg))
+        lb = max(lb, int(mx))
+        d = dist.to(torch.int64) & 0xFFFFFFFF
+        d[d == 0xFFFFFFFF] = -1
+        s = int(torch.argmax(d).item())
+    return lb
+
+
+def _pipeline(cd, dg, tau, seed, delta0=0, variant=0, step_cap=0, reps=3):
+    """Best-of-reps time of decompose + quotient + estimate; returns (stats,
+    (phi_gc, phi_approx), seconds, decompose seconds)."""
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, D, st = cd.cldiam_decompose(dg, tau, seed, delta0=delta0, variant=variant, step_cap=step_cap)
+        t1 = time.perf_counter()
+        q = cd.cldiam_build_quotient(dg, c, D)
+        est = cd.cldiam_estimate_diameter(q, st.radius)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if best is None or t2 - t0 < best[2]:
+            best = (st, est, t2 - t0, t1 - t0)
+    return best
+
+
+def variants_bench(args):
+    """CLUSTER (fixpoint growth), the literal step-synchronous variant and
+    CLUSTER2 on the road-like mesh: time, rounds/work, clusters and the
+    estimate's ratio to an iterated-SSSP lower bound on the diameter."""
+    import graphgen
+    import oracle   # only for the SSSP source rule shared with the tests
+    import paper_1506_03265_amd as cd
+    counts = json.load(open(os.path.join(HERE, "tests", "golden", "road4096_counts.json")))
+    log("[bench] generating road4096")
+    g = graphgen.road_like(4096, 1)
+    dg = cd.cldiam_load_csr(g)
+    lb = _sssp_lower_bound(cd, dg, oracle.sssp_source(g.n, counts["seed"]))
+    rows = {}
+    for name, var in (("cluster", cd.VARIANT_FIXPOINT), ("steps", cd.VARIANT_STEPS),
+                      ("cluster2", cd.VARIANT_CLUSTER2)):
+        st, est, t, td = _pipeline(cd, dg, counts["tau"], counts["seed"], variant=var, reps=args.steps)
+        ref = counts if name == "cluster" else counts[name]
+        ok = st.num_clusters == ref["num_clusters"] and est[1] == ref["phi_approx"]
+        if not ok:
+            log(f"[bench] {name} differs from the stored oracle values")
+            sys.exit(1)
+        rows[name] = {"ms": round(t * 1e3, 3), "decompose_ms": round(td * 1e3, 3), "clusters": st.num_clusters,
+                      "stages": st.stages, "levels": st.levels, "radius": st.radius, "phi_approx": est[1],
+                      "ratio_to_lower_bound": round(est[1] / lb, 4), "sweeps": st.sweeps}
+        if name == "steps":
+            rows[name].update(rounds=st.rounds, messages=st.messages, updates=st.updates)
+        if name == "cluster2":
+            rows[name].update(radius1=st.radius1)
+        log(f"[bench] {name}: {rows[name]}")
+    t = rows["cluster"]["ms"]
+    return {
+        "metric": "CLUSTER vs literal steps vs CLUSTER2 on the road-like mesh: ms per decompose+quotient+estimate",
+        "value": round(counts["edges"] / (t / 1e3) / 1e9, 6), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": 0, "ms_per_step": t, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": counts["text"] + f", tau={counts['tau']}, seed={counts['seed']}",
+                   "sssp_lower_bound": lb, "variants": rows},
+    }
+
+
+def delta0_bench(args):
+    """Initial-Delta experiment (Section 5): a 2048 x 2048 mesh whose edges
+    weigh 10^6 with probability 0.1 and 1 otherwise; CL-DIAM started from the
+    minimum weight, from the mean weight and from about the diameter."""
+    import graphgen
+    import oracle
+    import paper_1506_03265_amd as cd
+    side = args.side
+    log(f"[bench] generating the bimodal mesh {side}x{side}")
+    g = graphgen.bimodal_mesh(side, 1)
+    dg = cd.cldiam_load_csr(g)
+    lb = _sssp_lower_bound(cd, dg, oracle.sssp_source(g.n, 1))
+    mean = int(dg.weight_sum // max(g.m, 1))
+    rows = []
+    for label, d0 in (("min weight", 1), ("mean weight", mean), ("~diameter", lb)):
+        st, est, t, td = _pipeline(cd, dg, args.tau, 1, delta0=d0, reps=args.steps)
+        rows.append({"delta0": label, "value": d0, "ms": round(t * 1e3, 3), "levels": st.levels,
+                     "sweeps": st.sweeps, "stages": st.stages, "delta_end": st.delta_end,
+                     "clusters": st.num_clusters, "radius": st.radius, "phi_approx": est[1],
+                     "ratio_to_lower_bound": round(est[1] / lb, 4)})
+        log(f"[bench] delta0 {label}: {rows[-1]}")
+    return {
+        "metric": "initial-Delta experiment: approximation ratio to an SSSP lower bound and time per initial Delta",
+        "value": rows[1]["ratio_to_lower_bound"], "unit": "ratio", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": rows[1]["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{side}x{side} mesh, weights 10^6 w.p. 0.1 else 1, graph seed 1, tau={args.tau}",
+                   "n": g.n, "m_arcs": g.m, "sssp_lower_bound": lb, "runs": rows},
+    }
+
+
+def stepcap_bench(args):
+    """Growing-step cap O(n / tau) (Section 4): the literal step-synchronous
+    variant with caps of n/tau, n/(16 tau) and n/(256 tau) steps per
+    PartialGrowth call, on a mesh with skewed weights and on R-MAT."""
+    import graphgen
+    import oracle
+    import paper_1506_03265_amd as cd
+    out = {}
+    for gname, g in (("bimodal512", graphgen.bimodal_mesh(512, 2)), ("rmat18", graphgen.rmat(18, seed=2))):
+        dg = cd.cldiam_load_csr(g)
+        lb = _sssp_lower_bound(cd, dg, oracle.sssp_source(g.n, 1))
+        rows = []
+        for div in (0, 1, 16, 256):
+            cap = 0 if div == 0 else max(1, g.n // (args.tau * div))
+            st, est, t, td = _pipeline(cd, dg, args.tau, 1, variant=cd.VARIANT_STEPS, step_cap=cap, reps=args.steps)
+            rows.append({"step_cap": cap, "ms": round(t * 1e3, 3), "rounds": st.rounds, "messages": st.messages,
+                         "updates": st.updates, "stages": st.stages, "levels": st.levels,
+                         "clusters": st.num_clusters, "phi_approx": est[1],
+                         "ratio_to_lower_bound": round(est[1] / lb, 4)})
+            log(f"[bench] {gname} cap {cap}: {rows[-1]}")
+        out[gname] = {"n": g.n, "m_arcs": g.m, "sssp_lower_bound": lb, "runs": rows}
+    r = out["bimodal512"]["runs"][0]
+    return {
+        "metric": "growing-step cap: rounds, work and approximation ratio of the literal variant per cap",
+        "value": r["rounds"], "unit": "rounds", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": r["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic", "config": {"workload": f"tau={args.tau}", "graphs": out},
+    }
+
+
 def sssp_bench(args):
     import torch
 
@@ -343,11 +482,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="road4096", choices=["road4096", "rmat24", "rgg256", "serve", "sssp"])
+    ap.add_argument("--workload", default="road4096",
+                    choices=["road4096", "rmat24", "rgg256", "serve", "sssp", "variants", "delta0", "stepcap"])
+    ap.add_argument("--side", type=int, default=2048, help="delta0: mesh side")
+    ap.add_argument("--tau", type=int, default=4, help="delta0 / stepcap: tau")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--driver", type=int, default=0, help="0 auto, 1 host-driven, 2 persistent")
     ap.add_argument("--local-rounds", type=int, default=-1)
     ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--bucket-width", type=float, default=0.0,
+                    help="relaxation distance bucket in mean arc weights (0 default, < 0 none)")
     ap.add_argument("--decompose-only", action="store_true", help="time only the decomposition (for profiles)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer three times (reference kernel for HBM counters)")
@@ -380,6 +524,12 @@ def main():
         out = batched_bench(args)
     elif args.workload == "sssp":
         out = sssp_bench(args)
+    elif args.workload == "variants":
+        out = variants_bench(args)
+    elif args.workload == "delta0":
+        out = delta0_bench(args)
+    elif args.workload == "stepcap":
+        out = stepcap_bench(args)
     else:
         out = serve_bench(args)
     print(json.dumps(out), flush=True)

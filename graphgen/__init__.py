@@ -136,6 +136,18 @@ def road_like(side: int = 4096, seed: int = 1) -> Graph:
     return g
 
 
+def bimodal_mesh(side: int = 2048, seed: int = 1, heavy: int = 10**6) -> Graph:
+    """side x side mesh whose edges weigh `heavy` with probability 0.1 and 1
+    otherwise: the integer form (scaled by 10^6) of the mesh with weights 1
+    w.p. 0.1 and 10^-6 otherwise used for the initial-Delta experiment of
+    Section 5.  The weights come from the grid's uniform draws in [1, 10]:
+    the top value becomes `heavy`, the others 1."""
+    g = grid(side, side, 10, seed)
+    g.w = np.where(g.w == 10, np.uint32(heavy), np.uint32(1)).astype(np.uint32)
+    g.name = f"bimodal{side}"
+    return g
+
+
 def rmat(scale: int, seed: int = 1, edge_factor: int = 16, a=0.57, b=0.19, c=0.19, wbits: int = 20) -> Graph:
     """R-MAT graph, symmetrised and simple, largest component, weights in [1, 2^wbits]."""
     out = _CSR()

@@ -107,10 +107,44 @@ int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *h_weight_su
  * Outputs: d_cluster[v] = center node id of v's cluster (a center has
  * d_cluster[c] = c); d_D[v] as above. */
 typedef struct {
-  uint32_t tau;    /* >= 1 */
-  uint32_t delta0; /* initial Delta; 0 = floor(sum of arc weights / m) */
-  uint64_t seed;   /* Philox key */
+  uint32_t tau;      /* >= 1 */
+  uint32_t delta0;   /* initial Delta; 0 = floor(sum of arc weights / m) */
+  uint64_t seed;     /* Philox key */
+  uint32_t variant;  /* CLDIAM_VARIANT_* */
+  uint32_t step_cap; /* CLDIAM_VARIANT_STEPS: most Delta-growing steps per PartialGrowth call; 0 = no cap */
 } cldiam_params;
+
+/* CLDIAM_VARIANT_FIXPOINT (0): the behaviour described above (every Delta
+ * grown to its fixpoint, schedule-independent results).
+ * CLDIAM_VARIANT_STEPS (1): Procedure PartialGrowth of Algorithm 1 taken
+ * literally.  Growth runs in synchronous Delta-growing steps: all offers of a
+ * step are computed from the state before the step; a node accepts an offer
+ * only if its distance is strictly smaller than the node's own (among the
+ * offers of one step the smallest distance, then the smallest center, wins).
+ * A PartialGrowth call stops after a step that updates no state, or once at
+ * least half of the stage's uncovered nodes are covered, or after step_cap
+ * steps; Delta doubles one step at a time while fewer than half are covered
+ * (a stage whose growth has stopped with no uncovered node reachable keeps
+ * what it covered); if the new centers alone cover half, the stage performs
+ * no step.  The statistics then carry the paper's round and work counters:
+ * rounds (steps), messages (offers sent: every node updated by the previous
+ * step, or a source at a stage's or a Delta's first step, offers over each
+ * arc with d_u + w <= Delta) and updates (node states changed). */
+#define CLDIAM_VARIANT_FIXPOINT 0u
+#define CLDIAM_VARIANT_STEPS 1u
+/* CLDIAM_VARIANT_CLUSTER2 (2): CLUSTER2(G, tau) of Algorithm 2 (Section 4).
+ * First CLUSTER(G, tau) as above gives R_CL = max D; then iterations
+ * i = 1 .. ceil(log2 n): each uncovered node becomes a new center iff word 0
+ * of Philox4x32-10(counter = (v, i, 0, 1), key = seed) is below
+ * floor(min(1, 2^i / n) 2^32) (2^32 when 2^i >= n), and all clusters grow to
+ * the fixpoint with Delta2 = 2 R_CL.  Procedure Contract2 is implicit: a node
+ * assigned in the previous iteration at growth distance d_u offers its label
+ * at d_u + w - Delta2 over each edge with w <= Delta2 to an unassigned
+ * neighbour.  A node reached in iteration i by a cluster whose center was
+ * drawn in iteration j gets D = d + Delta2 (i - j), the length of a path from
+ * the center.  Statistics: stages = levels = iterations, delta_end = Delta2,
+ * radius = max D, radius1 = R_CL; Delta2 above 2^31 is CLDIAM_EOVERFLOW. */
+#define CLDIAM_VARIANT_CLUSTER2 2u
 
 typedef struct {
   int32_t stages;       /* executed stages */
@@ -127,6 +161,10 @@ typedef struct {
   int32_t grid_blocks;  /* workgroups of the persistent launch (0 = host-driven) */
   float kernel_ms;      /* device time of the job's control loop (HIP events) */
   int32_t iterations;   /* control steps of the whole job */
+  uint64_t rounds;      /* CLDIAM_VARIANT_STEPS: Delta-growing steps executed */
+  uint64_t messages;    /* CLDIAM_VARIANT_STEPS: offers sent */
+  uint64_t updates;     /* CLDIAM_VARIANT_STEPS: node states changed */
+  uint64_t radius1;     /* CLDIAM_VARIANT_CLUSTER2: radius R_CL of the preliminary CLUSTER run */
   /* per stage s < min(stages, CLDIAM_STAGE_LOG) */
   int32_t stage_uncovered[CLDIAM_STAGE_LOG];
   int32_t stage_centers[CLDIAM_STAGE_LOG];
@@ -144,7 +182,13 @@ typedef struct {
 typedef struct {
   int32_t local_rounds; /* workgroup-local relaxation rounds per sweep; < 0 = default (4) */
   int32_t grid_blocks;  /* workgroups per sweep; 0 = one per compute unit */
+  float bucket_width;   /* distance bucket of a relaxation sweep, in mean arc weights: a sweep relaxes
+                           only frontier nodes whose tentative distance is below (smallest distance on
+                           the frontier) + width, and keeps the others for later sweeps of the same
+                           growth; 0 = default (CLDIAM_BUCKET_DEFAULT), < 0 = no bucket */
+  int32_t reserved;     /* 0 */
 } cldiam_tuning;
+#define CLDIAM_BUCKET_DEFAULT 8.0f
 
 /* One graph description of a batch (graph operand in DEVICE memory). */
 typedef struct {

@@ -28,6 +28,7 @@ CLDIAM_ETIMEOUT = -6
 STAGE_LOG = 64
 
 DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
+VARIANT_FIXPOINT, VARIANT_STEPS, VARIANT_CLUSTER2 = 0, 1, 2
 
 EXPORTS = [
     "cldiam_strerror", "cldiam_last_error", "cldiam_version",
@@ -53,7 +54,8 @@ class _Csr(ctypes.Structure):
 
 
 class _Params(ctypes.Structure):
-    _fields_ = [("tau", ctypes.c_uint32), ("delta0", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+    _fields_ = [("tau", ctypes.c_uint32), ("delta0", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("variant", ctypes.c_uint32), ("step_cap", ctypes.c_uint32)]
 
 
 class _Graph(ctypes.Structure):
@@ -63,7 +65,8 @@ class _Graph(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("local_rounds", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+    _fields_ = [("local_rounds", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("bucket_width", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -71,7 +74,8 @@ class _Stats(ctypes.Structure):
                 ("delta_end", ctypes.c_uint32), ("stop", ctypes.c_int32), ("num_clusters", ctypes.c_int32),
                 ("singletons", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("radius", ctypes.c_uint64),
                 ("arcs_scanned", ctypes.c_uint64), ("status", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_float), ("iterations", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_float), ("iterations", ctypes.c_int32), ("rounds", ctypes.c_uint64),
+                ("messages", ctypes.c_uint64), ("updates", ctypes.c_uint64), ("radius1", ctypes.c_uint64),
                 ("stage_uncovered", ctypes.c_int32 * STAGE_LOG), ("stage_centers", ctypes.c_int32 * STAGE_LOG),
                 ("stage_covered", ctypes.c_int32 * STAGE_LOG), ("stage_delta", ctypes.c_uint32 * STAGE_LOG)]
 
@@ -220,6 +224,10 @@ class Stats:
     grid_blocks: int
     kernel_ms: float
     iterations: int
+    rounds: int = 0
+    messages: int = 0
+    updates: int = 0
+    radius1: int = 0
     stage_uncovered: list = field(default_factory=list)
     stage_centers: list = field(default_factory=list)
     stage_covered: list = field(default_factory=list)
@@ -230,7 +238,7 @@ def _stats(s: _Stats) -> Stats:
     k = min(s.stages, STAGE_LOG)
     return Stats(s.stages, s.levels, s.delta0, s.delta_end, s.stop, s.num_clusters, s.singletons, s.sweeps,
                  int(s.radius), int(s.arcs_scanned), s.status, s.grid_blocks, float(s.kernel_ms), s.iterations,
-                 list(s.stage_uncovered[:k]),
+                 int(s.rounds), int(s.messages), int(s.updates), int(s.radius1), list(s.stage_uncovered[:k]),
                  list(s.stage_centers[:k]), list(s.stage_covered[:k]), list(s.stage_delta[:k]))
 
 
@@ -238,7 +246,7 @@ class DecomposeJob:
     """Reusable decomposition launch: outputs, workspace and descriptors are
     allocated once so that repeated runs time only the device work."""
 
-    def __init__(self, graphs, params, driver=DRIVER_AUTO, local_rounds=-1, grid_blocks=0):
+    def __init__(self, graphs, params, driver=DRIVER_AUTO, local_rounds=-1, grid_blocks=0, bucket_width=0.0):
         torch = _torch()
         self.lib = load_library()
         self.graphs = list(graphs)
@@ -248,15 +256,17 @@ class DecomposeJob:
         G = len(self.graphs)
         self.desc = (_Graph * G)()
         for i, (g, p) in enumerate(zip(self.graphs, params)):
-            tau, seed, delta0 = p
+            tau, seed, delta0 = p[:3]
+            variant, step_cap = (tuple(p[3:5]) + (0, 0))[:2]
             self.desc[i] = _Graph(g.n, 0, g.m, g.row_ptr.data_ptr(), _ptr(g.arcs).value, g.weight_sum,
-                                  _Params(tau, delta0, seed), self.cluster[i].data_ptr(), self.D[i].data_ptr())
+                                  _Params(tau, delta0, seed, variant, step_cap), self.cluster[i].data_ptr(),
+                                  self.D[i].data_ptr())
         self.stats = (_Stats * G)()
         total_n = sum(g.n for g in self.graphs)
         self.wsb = self.lib.cldiam_decompose_workspace_size(total_n, G)
         self.ws = _ws(self.wsb, dev)
         self.driver = driver
-        self.tuning = _Tuning(local_rounds, grid_blocks)
+        self.tuning = _Tuning(local_rounds, grid_blocks, bucket_width, 0)
 
     def run(self, stream=None):
         _check(self.lib.cldiam_decompose_batch(len(self.graphs), self.desc, self.stats, self.driver,
@@ -266,17 +276,20 @@ class DecomposeJob:
 
 
 def cldiam_decompose(g: DeviceGraph, tau: int, seed: int, delta0: int = 0, driver=DRIVER_AUTO, stream=None,
-                     local_rounds=-1, grid_blocks=0):
+                     local_rounds=-1, grid_blocks=0, bucket_width=0.0, variant=0, step_cap=0):
     """CLUSTER(G, tau): returns (cluster int32 tensor, D int64 tensor holding
-    uint64 bit patterns, Stats)."""
-    job = DecomposeJob([g], [(tau, seed, delta0)], driver, local_rounds, grid_blocks)
+    uint64 bit patterns, Stats).  variant = VARIANT_STEPS runs PartialGrowth
+    literally (synchronous steps, per-step stop, optional step cap)."""
+    job = DecomposeJob([g], [(tau, seed, delta0, variant, step_cap)], driver, local_rounds, grid_blocks,
+                       bucket_width)
     st = job.run(stream)
     return job.cluster[0], job.D[0], st[0]
 
 
-def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None, local_rounds=-1, grid_blocks=0):
-    """Decomposes many graphs in one device job; params = [(tau, seed, delta0)]."""
-    job = DecomposeJob(graphs, params, driver, local_rounds, grid_blocks)
+def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None, local_rounds=-1, grid_blocks=0,
+                           bucket_width=0.0):
+    """Decomposes many graphs in one device job; params = [(tau, seed, delta0[, variant, step_cap])]."""
+    job = DecomposeJob(graphs, params, driver, local_rounds, grid_blocks, bucket_width)
     st = job.run(stream)
     return job.cluster, job.D, st
 
@@ -290,6 +303,7 @@ class Server:
     handed back by poll."""
 
     def __init__(self, node_capacity: int, max_graphs: int = 64, local_rounds: int = -1, grid_blocks: int = 0,
+                 bucket_width: float = 0.0,
                  device="cuda", stream=None):
         torch = _torch()
         self.lib = load_library()
@@ -299,17 +313,19 @@ class Server:
         self.ws = _ws(self.wsb, device)
         self.ptr = ctypes.c_void_p()
         _check(self.lib.cldiam_server_create(ctypes.byref(self.ptr), node_capacity, max_graphs,
-                                             ctypes.byref(_Tuning(local_rounds, grid_blocks)), _ptr(self.ws), self.wsb,
+                                             ctypes.byref(_Tuning(local_rounds, grid_blocks, bucket_width, 0)),
+                                             _ptr(self.ws), self.wsb,
                                              ctypes.c_void_p(self.stream.cuda_stream)), "cldiam_server_create")
         self.outputs = {}
         self.max_graphs = max_graphs
 
-    def submit(self, g: DeviceGraph, tau: int, seed: int, tag: int, delta0: int = 0):
+    def submit(self, g: DeviceGraph, tau: int, seed: int, tag: int, delta0: int = 0, variant: int = 0,
+               step_cap: int = 0):
         torch = _torch()
         cluster = torch.empty(g.n, dtype=torch.int32, device=self.device)
         D = torch.empty(g.n, dtype=torch.int64, device=self.device)
         desc = _Graph(g.n, 0, g.m, g.row_ptr.data_ptr(), _ptr(g.arcs).value, g.weight_sum,
-                      _Params(tau, delta0, seed), cluster.data_ptr(), D.data_ptr())
+                      _Params(tau, delta0, seed, variant, step_cap), cluster.data_ptr(), D.data_ptr())
         _check(self.lib.cldiam_server_submit(self.ptr, ctypes.byref(desc), tag), "cldiam_server_submit")
         self.outputs[tag] = (g, cluster, D)
 

@@ -76,6 +76,12 @@ enum Phase : uint32_t {
   PH_SINGLE = 7,
   PH_DONE = 8,
   PH_IDLE = 9,   // empty slot of a server job
+  PH_COMMIT = 10,  // synchronous steps: publish the step's updates
+  PH_MERGE = 11,   // synchronous steps: add the blocked list to the active list
+  PH_C2_INIT = 12,      // CLUSTER2: fresh state for every node
+  PH_C2_SELECT = 13,    // CLUSTER2: centers of iteration i with probability 2^i / n
+  PH_C2_BOUNDARY = 14,  // CLUSTER2: Contract2's rescaled edges out of last iteration's clusters
+  PH_C2_ASSIGN = 15,    // CLUSTER2: assignment, D = d + Delta2 (i - birth iteration)
 };
 
 struct GDesc {
@@ -89,6 +95,10 @@ struct GDesc {
   int32_t n;
   uint32_t stop;     // ceil(8 tau log2 n)
   uint32_t delta0;
+  uint32_t bucket;   // distance bucket width of RELAX sweeps; 0 = unbounded
+  uint32_t variant;  // CLDIAM_VARIANT_*
+  uint32_t step_cap; // synchronous steps: most steps per PartialGrowth call (0 = none)
+  uint32_t c2_iters; // CLUSTER2: ceil(log2 n) iterations
   uint32_t pad;
 };
 
@@ -100,6 +110,14 @@ struct GState {
   uint32_t fcur, fnxt, blk;
   int32_t status;
   uint32_t levels, sweeps, centers_total, singletons;
+  uint32_t theta;    // RELAX sweeps relax frontier nodes with tentative distance below theta
+  // synchronous steps
+  uint32_t steps_call;  // steps of the current PartialGrowth call
+  uint32_t fid;         // sweep id that stamped the current active list
+  uint32_t after;       // phase after a MERGE sweep
+  uint32_t c2;          // 1 while in CLUSTER2's iterations
+  uint64_t rounds, updates;
+  uint64_t radius1;     // CLUSTER2: R_CL of the preliminary CLUSTER run
 };
 
 struct alignas(128) PadU32 {
@@ -119,6 +137,8 @@ struct GCount {
   PadU32 centers;  // centers drawn in this stage
   PadU64 next;     // NEXT: smallest reach distance
   PadU64 radius;   // max D
+  PadU32 fmin;     // RELAX: smallest tentative distance pushed on the next frontier
+  PadU64 msgs;     // synchronous steps: offers sent
 };
 
 struct Ctl {
@@ -143,6 +163,7 @@ struct Job {
                      // [2G+1, 3G]: items of the graph in this sweep
   int32_t *log;      // G x CLDIAM_STAGE_LOG x 4
   uint64_t *key;
+  uint64_t *keyn;    // synchronous steps: state after the current step (key holds the state before it)
   uint64_t *R;
   uint32_t *fstamp;
   uint32_t *bstamp;
@@ -169,10 +190,12 @@ constexpr uint32_t kPassChunk = kThreads;   // smallest chunk of a node pass (SE
 
 __device__ uint32_t items_of(const GState &s, const GCount &c) {
   switch (s.phase) {
-    case PH_SELECT: case PH_COMPACT: case PH_SINGLE: return c.cntU[s.ucur].v;
+    case PH_SELECT: case PH_COMPACT: case PH_SINGLE: case PH_ASSIGN: case PH_RMAX: return c.cntU[s.ucur].v;
     case PH_RELAX: return c.cnt[s.fcur].v;
-    case PH_NEXT: return c.cnt[s.blk].v;
-    case PH_ASSIGN: case PH_RMAX: return c.cntC.v;
+    case PH_NEXT: case PH_MERGE: return c.cnt[s.blk].v;
+    case PH_COMMIT: return c.cnt[s.fnxt].v;
+    case PH_C2_SELECT: case PH_C2_ASSIGN: return c.cntU[s.ucur].v;
+    case PH_C2_BOUNDARY: return c.cnt[s.blk].v;
     default: return 0;
   }
 }
@@ -200,6 +223,47 @@ __device__ void begin_stage(const GDesc &d, GState &s, GCount &c, Ctl *ctl) {
   s.phase = PH_SELECT;
 }
 
+// Upper end (exclusive) of the distance bucket that starts at lo.
+__device__ __forceinline__ uint32_t bucket_limit(const GDesc &d, uint32_t lo) {
+  if (d.bucket == 0) return 0xffffffffu;
+  const uint64_t t = (uint64_t)lo + d.bucket;
+  return t < 0xffffffffull ? (uint32_t)t : 0xffffffffu;
+}
+
+// CLUSTER2: iteration s.stage + 1 draws centers with probability 2^i / n.
+__device__ void c2_begin_iteration(const GDesc &d, GState &s, GCount &c) {
+  const int i = (int)s.stage + 1;
+  const double p = ldexp(1.0, i) / (double)d.n;
+  s.T = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(p * 4294967296.0);
+  c.centers.v = 0;
+  c.cntC.v = 0;
+  s.phase = PH_C2_SELECT;
+}
+
+// Synchronous steps: a new PartialGrowth call at the current Delta.
+__device__ __forceinline__ void begin_call(GState &s, uint32_t sweep_id) {
+  s.levels++;
+  s.level_id = sweep_id;
+  s.steps_call = 0;
+  s.theta = 0xffffffffu;
+  s.phase = PH_RELAX;
+}
+
+// Synchronous steps: add the blocked list to the active list, then `after`.
+__device__ __forceinline__ void merge_then(GState &s, uint32_t after) {
+  s.after = after;
+  s.phase = PH_MERGE;
+}
+
+__device__ __forceinline__ bool double_delta(GState &s, Ctl *ctl) {
+  if (2ull * s.delta > CLD_DELTA_MAX) {
+    fail(s, ctl, CLDIAM_EOVERFLOW);
+    return false;
+  }
+  s.delta *= 2;
+  return true;
+}
+
 // Per-graph transition after a sweep of its current phase.
 __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
   const GDesc &d = job.desc[g];
@@ -219,24 +283,76 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       begin_stage(d, s, c, job.ctl);
       break;
     case PH_SELECT:
-      // frontier = sources from the previous stage + the new centers
+      // frontier = sources from the previous stage + the new centers, all at
+      // distance 0
       s.centers_total += c.centers.v;
+      if (d.variant == CLDIAM_VARIANT_STEPS) {
+        // the outer loop's test comes first: enough new centers end the stage
+        if (2ull * c.cntC.v >= (uint64_t)s.nU) { s.phase = PH_ASSIGN; break; }
+        begin_call(s, sweep_id);
+        break;
+      }
       s.level_id = sweep_id;
       s.levels++;
+      s.theta = bucket_limit(d, 0);
+      c.fmin.v = 0xffffffffu;
       s.phase = PH_RELAX;
       break;
     case PH_RELAX:
       s.sweeps++;
+      if (d.variant == CLDIAM_VARIANT_STEPS) {
+        s.rounds++;
+        s.steps_call++;
+        s.fid = sweep_id - 1;   // the stamp of the step's updated nodes
+        s.phase = PH_COMMIT;
+        break;
+      }
       if (c.cnt[s.fnxt].v > 0) {
         uint32_t t = s.fcur; s.fcur = s.fnxt; s.fnxt = t;
         c.cnt[s.fnxt].v = 0;
+        // the next bucket starts at the smallest distance on the frontier
+        const uint32_t th = c.fmin.v == 0xffffffffu ? 0xffffffffu : bucket_limit(d, c.fmin.v);
+        if (th > s.theta) s.theta = th;
+        c.fmin.v = 0xffffffffu;
       } else {
         c.cnt[s.fcur].v = 0;
-        if (2ull * c.cntC.v >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
+        if (s.c2) s.phase = PH_C2_ASSIGN;
+        else if (2ull * c.cntC.v >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
         else { c.next.v = CLD_INF64; s.phase = PH_NEXT; }
       }
       break;
+    case PH_COMMIT: {
+      const uint32_t nn = c.cnt[s.fnxt].v;
+      s.updates += nn;
+      uint32_t t = s.fcur; s.fcur = s.fnxt; s.fnxt = t;   // the updated nodes are the next active set
+      c.cnt[s.fnxt].v = 0;
+      if (nn > 0 && 2ull * c.cntC.v >= (uint64_t)s.nU) {
+        merge_then(s, PH_ASSIGN);
+      } else if (nn > 0 && d.step_cap && s.steps_call >= d.step_cap) {
+        if (!double_delta(s, job.ctl)) break;
+        merge_then(s, PH_RELAX);
+      } else if (nn > 0) {
+        s.phase = PH_RELAX;
+      } else {
+        c.next.v = CLD_INF64;   // fixpoint: is any uncovered node reachable?
+        s.phase = PH_NEXT;
+      }
+      break;
+    }
+    case PH_MERGE:
+      c.cnt[s.blk].v = 0;
+      if (s.after == PH_RELAX) begin_call(s, sweep_id);
+      else s.phase = s.after;
+      break;
     case PH_NEXT:
+      if (d.variant == CLDIAM_VARIANT_STEPS) {
+        if (c.next.v == CLD_INF64) {
+          merge_then(s, PH_ASSIGN);
+        } else if (double_delta(s, job.ctl)) {
+          merge_then(s, PH_RELAX);
+        }
+        break;
+      }
       if (c.next.v == CLD_INF64) {
         s.phase = PH_ASSIGN;
       } else {
@@ -251,6 +367,8 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
         c.cnt[s.blk].v = 0;
         s.level_id = sweep_id;
+        s.theta = bucket_limit(d, (uint32_t)c.next.v);
+        c.fmin.v = 0xffffffffu;
         s.phase = PH_RELAX;
       }
       break;
@@ -269,8 +387,20 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       s.ucur ^= 1;
       s.nU = c.cntU[s.ucur].v;
       s.stage++;
-      // sources of the next stage: the blocked list of the last level
-      uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
+      if (s.c2) {
+        // the blocked list stays: next iteration's Contract2 boundary
+        c.cnt[s.fcur].v = 0;
+        c.cnt[s.fnxt].v = 0;
+        if (s.stage >= d.c2_iters) s.phase = PH_DONE;
+        else c2_begin_iteration(d, s, c);
+        break;
+      }
+      if (d.variant != CLDIAM_VARIANT_STEPS) {
+        // sources of the next stage: the blocked list of the last level
+        uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
+      }
+      // (synchronous steps: the active list, merged with the blocked list,
+      // already holds them)
       c.cnt[s.blk].v = 0;
       c.cnt[s.fnxt].v = 0;
       begin_stage(d, s, c, job.ctl);
@@ -279,6 +409,45 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
     case PH_SINGLE:
       s.singletons = s.nU;
       s.phase = PH_DONE;
+      if (d.variant == CLDIAM_VARIANT_CLUSTER2) {
+        // CLUSTER2 on top of the finished CLUSTER run
+        const uint64_t r1 = c.radius.v;
+        if (2 * r1 > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); break; }
+        s.radius1 = r1;
+        s.delta = (uint32_t)(2 * r1);
+        if (d.c2_iters == 0) break;   // one node: its own cluster
+        s.c2 = 1;
+        s.stage = 0;
+        s.levels = 0;
+        s.centers_total = 0;
+        s.singletons = 0;
+        c.radius.v = 0;
+        s.phase = PH_C2_INIT;
+      }
+      break;
+    case PH_C2_INIT:
+      s.nU = (uint32_t)d.n;
+      s.ucur = 0;
+      c.cntU[0].v = (uint32_t)d.n;
+      c.cnt[0].v = c.cnt[1].v = c.cnt[2].v = 0;
+      c2_begin_iteration(d, s, c);
+      break;
+    case PH_C2_SELECT:
+      s.centers_total += c.centers.v;
+      s.levels++;
+      s.phase = PH_C2_BOUNDARY;
+      break;
+    case PH_C2_BOUNDARY:
+      // the boundary list is consumed; growth marks a fresh one
+      c.cnt[s.blk].v = 0;
+      s.level_id = sweep_id;
+      s.theta = bucket_limit(d, 0);
+      c.fmin.v = 0xffffffffu;
+      s.phase = PH_RELAX;
+      break;
+    case PH_C2_ASSIGN:
+      c.cntU[s.ucur ^ 1].v = 0;
+      s.phase = PH_COMPACT;
       break;
     default:
       break;
@@ -306,7 +475,8 @@ __device__ void control_block(const Job &job) {
       if (ctl->error == 0 || job.st[g].phase == PH_DONE) control_graph(job, g, sweep_id);
       if (ctl->error != 0 && job.st[g].phase != PH_DONE) job.st[g].phase = PH_DONE;
       const uint32_t phase = job.st[g].phase;
-      const uint32_t n_items = items_of(job.st[g], job.cn[g]);
+      const uint32_t n_items =
+          job.st[g].phase == PH_C2_INIT ? (uint32_t)job.desc[g].n : items_of(job.st[g], job.cn[g]);
       // Every graph is cut into its own chunks, at most one per workgroup, so
       // that the frontier of each graph is spread over the whole grid whatever
       // the other graphs of the job are doing (a node pass of millions of
@@ -361,6 +531,7 @@ struct Stage {
   unsigned long long acc;   // min (NEXT) or max (ASSIGN) accumulator
   uint32_t acc32;           // centers drawn (SELECT)
   uint32_t flush;           // a list passed the flush threshold
+  uint32_t fmin;            // RELAX: smallest distance pushed on the next frontier
 };
 
 struct Out {
@@ -399,6 +570,17 @@ __device__ void stage_flush(Stage &S, const Out *out, int nout) {
   __syncthreads();
 }
 
+// Synchronous step for one active node u (see relax_one_sync).  Returns the
+// number of offers sent (arcs with d_u + w <= Delta).
+__device__ __forceinline__ uint32_t relax_sync(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
+                                               uint32_t it, uint32_t level_id, int32_t u, Stage &S,
+                                               const Out *out);
+
+// Smallest tentative distance pushed on the next frontier by this workgroup.
+__device__ __forceinline__ void note_fmin(Stage &S, uint32_t dist) {
+  if (dist < S.fmin) atomicMin(&S.fmin, dist);
+}
+
 // RELAX: scan the light prefix of u's row (w <= Delta - d_u) and offer
 // (d_u + w, c_u) to every neighbour.  Outputs: 0 next frontier, 1 covered,
 // 2 blocked.  Arcs are handled four at a time so that their key loads and
@@ -425,12 +607,21 @@ __device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v
 }
 
 __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
-                                               uint32_t it, uint32_t level_id, int32_t u, Stage &S,
-                                               const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+                                               uint32_t theta, uint32_t it, uint32_t level_id, int32_t u,
+                                               Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+  const uint64_t ku = job.key[off + u];
+  if ((uint32_t)(ku >> 32) >= theta) {
+    // beyond the current distance bucket: stays on the frontier for a later
+    // sweep (it may already be there if it improved in this sweep)
+    if (atomicExch(&job.fstamp[off + u], it) != it) {
+      stage_push(S, out, 0, u);
+      note_fmin(S, (uint32_t)(ku >> 32));
+    }
+    return 0;
+  }
   const int32_t a0 = d.row_ptr[u];
   const int32_t a1 = d.row_ptr[u + 1];
   if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
-  const uint64_t ku = job.key[off + u];
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
   uint32_t scanned = 0;
@@ -466,10 +657,57 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
 #pragma unroll
     for (int j = 0; j < kArcBatch; ++j) {
       const int32_t v = (int32_t)(uint32_t)arc[j];
-      if (front[j]) stage_push(S, out, 0, v);
+      if (front[j]) {
+        stage_push(S, out, 0, v);
+        note_fmin(S, (uint32_t)(ku >> 32) + (uint32_t)(arc[j] >> 32));
+      }
       if (!ok[j]) continue;
       if (cur[j] == CLD_INF64) stage_push(S, out, 1, v);
       if (lq) lq_push(lq_cnt, lq, v);
+    }
+  }
+  if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
+    stage_push(S, out, 2, u);
+  return scanned;
+}
+
+__device__ __forceinline__ uint32_t relax_sync(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
+                                               uint32_t it, uint32_t level_id, int32_t u, Stage &S,
+                                               const Out *out) {
+  const int32_t a0 = d.row_ptr[u];
+  const int32_t a1 = d.row_ptr[u + 1];
+  if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
+  const uint64_t ku = job.key[off + u];
+  const uint32_t lim = delta - (uint32_t)(ku >> 32);
+  bool blocked = false;
+  uint32_t scanned = 0;
+  for (int32_t base = a0; base < a1 && !blocked; base += kArcBatch) {
+    uint64_t arc[kArcBatch], cur[kArcBatch], old[kArcBatch];
+    bool ok[kArcBatch], front[kArcBatch];
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < a1 ? d.arcs[base + j] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const bool in = base + j < a1;
+      ok[j] = in && (uint32_t)(arc[j] >> 32) <= lim;
+      if (in && !ok[j]) blocked = true;
+      scanned += ok[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) cur[j] = ok[j] ? job.key[off + (int32_t)(uint32_t)arc[j]] : 0ull;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const uint64_t cand = ku + (arc[j] & 0xffffffff00000000ull);
+      ok[j] = ok[j] && (cand >> 32) < (cur[j] >> 32);
+      const int64_t gv = off + (int32_t)(uint32_t)arc[j];
+      old[j] = ok[j] ? atomicMin((unsigned long long *)&job.keyn[gv], (unsigned long long)cand) : 0ull;
+      front[j] = ok[j] && atomicExch(&job.fstamp[gv], it) != it;
+    }
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const int32_t v = (int32_t)(uint32_t)arc[j];
+      if (front[j]) stage_push(S, out, 0, v);
+      if (ok[j] && old[j] == CLD_INF64) stage_push(S, out, 1, v);
     }
   }
   if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
@@ -485,11 +723,29 @@ __device__ __forceinline__ void relax_one(const Job &job, int64_t off, uint64_t 
   const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
   if (cand < job.key[gv]) {
     const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
-    if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
+    if (atomicExch(&job.fstamp[gv], it) != it) {
+      stage_push(S, out, 0, v);
+      note_fmin(S, (uint32_t)(cand >> 32));
+    }
     if (cand < old) {
       if (old == CLD_INF64) stage_push(S, out, 1, v);
       if (lq) lq_push(lq_cnt, lq, v);
     }
+  }
+}
+
+// Synchronous steps: an offer is judged against the state before the step
+// (key) and applied to the state after it (keyn); only a strictly smaller
+// distance is accepted, the lexicographic minimum over the step's offers wins.
+__device__ __forceinline__ void relax_one_sync(const Job &job, int64_t off, uint64_t ku, uint64_t arc, uint32_t it,
+                                               Stage &S, const Out *out) {
+  const int32_t v = (int32_t)(uint32_t)arc;
+  const int64_t gv = off + v;
+  const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
+  if ((cand >> 32) < (job.key[gv] >> 32)) {
+    const uint64_t old = atomicMin((unsigned long long *)&job.keyn[gv], (unsigned long long)cand);
+    if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
+    if (old == CLD_INF64) stage_push(S, out, 1, v);
   }
 }
 
@@ -519,9 +775,9 @@ __device__ __forceinline__ uint64_t next_small(const Job &job, const GDesc &d, i
 
 // Cooperative passes over the rows deferred in this round: each wave takes
 // whole mid-size rows (64 arcs per step), then the whole workgroup takes each
-// big row (blockDim arcs per step).  mode 0 relaxes the light prefix; mode 1
-// (NEXT) finds the first heavy arc into an unreached node and folds d_u + w
-// into S.acc.
+// big row (blockDim arcs per step).  mode 0 relaxes the light prefix; mode 2
+// does the same as a synchronous step; mode 1 (NEXT) finds the first heavy arc
+// into an unreached node and folds d_u + w into S.acc.
 __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint32_t delta, uint32_t it,
                               uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq, int mode) {
   __syncthreads();
@@ -534,7 +790,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
     const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
     const uint64_t ku = job.key[off + u];
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
-    if (mode == 0) {
+    if (mode != 1) {
       for (int32_t base = a0; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
         const uint64_t arc = a < a1 ? d.arcs[a] : ~0ull;
@@ -542,7 +798,8 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
         if (!__any(light)) break;
         if (light) {
           ++scanned;
-          relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq);
+          if (mode == 2) relax_one_sync(job, off, ku, arc, it, S, out);
+          else relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq);
         }
       }
       if (lane == 0 && (uint32_t)(d.arcs[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
@@ -573,10 +830,11 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       const int32_t mid = lo + ((hi - lo) >> 1);
       if ((uint32_t)(d.arcs[mid] >> 32) <= lim) lo = mid + 1; else hi = mid;
     }
-    if (mode == 0) {
+    if (mode != 1) {
       for (int32_t a = a0 + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
         ++scanned;
-        relax_one(job, off, ku, d.arcs[a], it, S, out, lq_cnt, lq);
+        if (mode == 2) relax_one_sync(job, off, ku, d.arcs[a], it, S, out);
+        else relax_one(job, off, ku, d.arcs[a], it, S, out, lq_cnt, lq);
       }
       if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
       // keep LDS staging within bounds between rows
@@ -611,6 +869,38 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   return scanned;
 }
 
+// CLUSTER2, Contract2: u was assigned last iteration at growth distance dl
+// (kept in keyn) with label c; every edge with Delta2 - dl < w <= Delta2 is
+// the rescaled edge (c, v) of weight dl + w - Delta2.  Rows are sorted by
+// weight, so those arcs are one contiguous range.
+__device__ uint32_t c2_boundary(const Job &job, const GDesc &d, int64_t off, uint32_t delta2, uint32_t it, int32_t u,
+                                Stage &S, const Out *out) {
+  const uint32_t dl = (uint32_t)job.keyn[off + u];
+  const uint64_t label = job.key[off + u] & 0xffffffffull;
+  const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
+  int32_t lo = a0, hi = a1;
+  while (lo < hi) {   // first arc with w > delta2 - dl
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint32_t)(d.arcs[mid] >> 32) <= delta2 - dl) lo = mid + 1; else hi = mid;
+  }
+  uint32_t scanned = 0;
+  for (int32_t a = lo; a < a1; ++a) {
+    const uint64_t arc = d.arcs[a];
+    const uint32_t w = (uint32_t)(arc >> 32);
+    if (w > delta2) break;
+    ++scanned;
+    const int32_t v = (int32_t)(uint32_t)arc;
+    const int64_t gv = off + v;
+    const uint64_t cand = ((uint64_t)(dl + w - delta2) << 32) | label;
+    if (cand < job.key[gv]) {
+      const uint64_t old = atomicMin((unsigned long long *)&job.key[gv], (unsigned long long)cand);
+      if (atomicExch(&job.fstamp[gv], it) != it) stage_push(S, out, 0, v);
+      if (old == CLD_INF64) stage_push(S, out, 1, v);
+    }
+  }
+  return scanned;
+}
+
 // Items [a, b) of the index space, all of graph g.
 __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, uint32_t it, Stage &S) {
   const GDesc &d = job.desc[g];
@@ -618,7 +908,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   GCount &cn = job.cn[g];
   const int64_t off = d.off;
   const uint32_t phase = s.phase;
-  const uint32_t delta = s.delta, level_id = s.level_id, stage = s.stage, ucur = s.ucur;
+  const uint32_t delta = s.delta, level_id = s.level_id, stage = s.stage, ucur = s.ucur, theta = s.theta;
   const uint32_t fcur = s.fcur, fnxt = s.fnxt, blk = s.blk;
   const uint64_t T = s.T;
   Out out[3];
@@ -639,12 +929,24 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       out[0] = {job.U[ucur ^ 1] + off, &cn.cntU[ucur ^ 1].v};
       nout = 1;
       break;
+    case PH_MERGE:
+      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      nout = 1;
+      break;
+    case PH_C2_SELECT:
+    case PH_C2_BOUNDARY:
+      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      out[1] = {job.C + off, &cn.cntC.v};
+      nout = 2;
+      break;
     default:
       break;
   }
+  const bool steps = d.variant == CLDIAM_VARIANT_STEPS;
   if (threadIdx.x == 0) {
     S.acc = (phase == PH_NEXT) ? CLD_INF64 : 0ull;
     S.acc32 = 0;
+    S.fmin = 0xffffffffu;
     S.lq_cnt[0] = 0;
     S.lq_cnt[1] = 0;
     S.mid_cnt = 0;
@@ -662,6 +964,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           const uint32_t x0 = cld_philox_word0((uint32_t)v, stage, 0u, 0u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
           if ((uint64_t)x0 < T) {
             job.key[off + v] = (uint64_t)(uint32_t)v;
+            job.keyn[off + v] = (uint64_t)(uint32_t)v;
             stage_push(S, out, 0, v);
             stage_push(S, out, 1, v);
             atomicAdd(&S.acc32, 1u);
@@ -669,9 +972,56 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
         }
         case PH_RELAX:
-          scanned += relax_item(job, d, off, delta, it, level_id, job.pool[fcur][off + idx], S, out, &S.lq_cnt[0],
-                                S.lq[0]);
+          if (steps)
+            scanned += relax_sync(job, d, off, delta, it, level_id, job.pool[fcur][off + idx], S, out);
+          else
+            scanned += relax_item(job, d, off, delta, theta, it, level_id, job.pool[fcur][off + idx], S, out,
+                                  &S.lq_cnt[0], S.lq[0]);
           break;
+        case PH_COMMIT: {
+          const int32_t v = job.pool[fnxt][off + idx];
+          job.key[off + v] = job.keyn[off + v];
+          break;
+        }
+        case PH_MERGE: {
+          const int32_t u = job.pool[blk][off + idx];
+          if (atomicExch(&job.fstamp[off + u], s.fid) != s.fid) stage_push(S, out, 0, u);
+          break;
+        }
+        case PH_C2_INIT:
+          job.key[off + idx] = CLD_INF64;
+          job.U[0][off + idx] = (int32_t)idx;
+          break;
+        case PH_C2_SELECT: {
+          const int32_t v = job.U[ucur][off + idx];
+          const uint32_t x0 =
+              cld_philox_word0((uint32_t)v, stage + 1, 0u, 1u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+          if ((uint64_t)x0 < T) {
+            job.key[off + v] = (uint64_t)(uint32_t)v;
+            job.R[off + v] = stage + 1;   // birth iteration of the center
+            stage_push(S, out, 0, v);
+            stage_push(S, out, 1, v);
+            atomicAdd(&S.acc32, 1u);
+          }
+          break;
+        }
+        case PH_C2_BOUNDARY:
+          scanned += c2_boundary(job, d, off, delta, it, job.pool[blk][off + idx], S, out);
+          break;
+        case PH_C2_ASSIGN: {
+          const int32_t v = job.U[ucur][off + idx];
+          const uint64_t k = job.key[off + v];
+          if (k == CLD_INF64) break;
+          const uint32_t c = (uint32_t)k;
+          const uint64_t local = k >> 32;
+          const uint64_t Dv = local + (uint64_t)delta * (uint64_t)(stage + 1 - job.R[off + c]);
+          d.cluster[v] = (int32_t)c;
+          d.D[v] = Dv;
+          job.keyn[off + v] = local;   // kept for next iteration's rescaled edges
+          job.key[off + v] = (uint64_t)c;
+          if (Dv > S.acc) atomicMax(&S.acc, (unsigned long long)Dv);
+          break;
+        }
         case PH_NEXT: {
           const int32_t u = job.pool[blk][off + idx];
           const int32_t deg = d.row_ptr[u + 1] - d.row_ptr[u];
@@ -681,8 +1031,12 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
         }
         case PH_ASSIGN: {
-          const int32_t v = job.C[off + idx];
+          // over the stage's uncovered list (in node order at the first
+          // stage, so these reads and writes are coalesced); covered nodes
+          // are the ones with a finite key
+          const int32_t v = job.U[ucur][off + idx];
           const uint64_t k = job.key[off + v];
+          if (k == CLD_INF64) break;
           const uint32_t c = (uint32_t)k;
           const uint64_t Dv = (k >> 32) + job.R[off + c];
           d.cluster[v] = (int32_t)c;
@@ -691,12 +1045,15 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
         }
         case PH_RMAX: {
-          const int32_t v = job.C[off + idx];
-          const uint32_t c = (uint32_t)job.key[off + v];
+          const int32_t v = job.U[ucur][off + idx];
+          const uint64_t k = job.key[off + v];
+          if (k == CLD_INF64) break;
+          const uint32_t c = (uint32_t)k;
           const uint64_t Dv = d.D[v];
           uint64_t *rr = &job.R[off + c];
           if (Dv > *rr) atomicMax((unsigned long long *)rr, (unsigned long long)Dv);
           job.key[off + v] = (uint64_t)c;
+          job.keyn[off + v] = (uint64_t)c;
           break;
         }
         case PH_COMPACT: {
@@ -715,7 +1072,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       }
     }
     if (phase == PH_RELAX || phase == PH_NEXT)
-      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[0], S.lq[0], phase == PH_NEXT);
+      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, steps ? nullptr : &S.lq_cnt[0],
+                           steps ? nullptr : S.lq[0], phase == PH_NEXT ? 1 : (steps ? 2 : 0));
     if (nout) {
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -723,7 +1081,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       if (S.flush) stage_flush(S, out, nout);
     }
   }
-  if (phase == PH_RELAX) {
+  if (phase == PH_RELAX && steps && scanned) atomicAdd(&S.acc, (unsigned long long)scanned);
+  if (phase == PH_RELAX && !steps) {
     // Local rounds: keep relaxing the neighbours this workgroup improved.
     // Every improved node is also on the global next frontier, so these
     // rounds only move the fixpoint closer; dropped overflow loses nothing.
@@ -735,7 +1094,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       if (threadIdx.x == 0) S.lq_cnt[q ^ 1] = 0;
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
-        scanned += relax_item(job, d, off, delta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
+        scanned += relax_item(job, d, off, delta, theta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1],
+                              S.lq[q ^ 1]);
       scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0);
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -748,8 +1108,10 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   __syncthreads();
   if (threadIdx.x == 0) {
     if (phase == PH_NEXT && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
-    if (phase == PH_ASSIGN && S.acc) atomicMax(&cn.radius.v, S.acc);
-    if (phase == PH_SELECT && S.acc32) atomicAdd(&cn.centers.v, S.acc32);
+    if ((phase == PH_ASSIGN || phase == PH_C2_ASSIGN) && S.acc) atomicMax(&cn.radius.v, S.acc);
+    if ((phase == PH_SELECT || phase == PH_C2_SELECT) && S.acc32) atomicAdd(&cn.centers.v, S.acc32);
+    if (phase == PH_RELAX && S.fmin != 0xffffffffu) atomicMin(&cn.fmin.v, S.fmin);
+    if (phase == PH_RELAX && steps && S.acc) atomicAdd(&cn.msgs.v, S.acc);
   }
   __syncthreads();
   return scanned;
@@ -793,6 +1155,7 @@ __global__ void __launch_bounds__(256) k_init(Job job, int64_t total_n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += stride) {
     job.key[i] = CLD_INF64;
+    job.keyn[i] = CLD_INF64;
     job.R[i] = 0;
     job.fstamp[i] = 0;
     job.bstamp[i] = 0;
@@ -810,6 +1173,7 @@ __global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     job.key[off + i] = CLD_INF64;
+    job.keyn[off + i] = CLD_INF64;
     job.R[off + i] = 0;
     job.fstamp[off + i] = 0;
     job.bstamp[off + i] = 0;
@@ -846,7 +1210,7 @@ struct Layout {
   Ctl *ctl;
   uint32_t *seg;
   int32_t *log;
-  uint64_t *key, *R;
+  uint64_t *key, *keyn, *R;
   uint32_t *fstamp, *bstamp;
   int32_t *pool[3], *U[2], *C;
 };
@@ -860,6 +1224,7 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto p_seg = a.template take<uint32_t>(3 * (size_t)G + 1);
   auto p_log = a.template take<int32_t>((size_t)G * CLDIAM_STAGE_LOG * 4);
   auto p_key = a.template take<uint64_t>(N);
+  auto p_keyn = a.template take<uint64_t>(N);
   auto p_R = a.template take<uint64_t>(N);
   auto p_fs = a.template take<uint32_t>(N);
   auto p_bs = a.template take<uint32_t>(N);
@@ -871,7 +1236,7 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto c = a.template take<int32_t>(N);
   if (L) {
     *L = Layout{(GDesc *)p_desc, (GState *)p_st, (GCount *)p_cn, (Ctl *)p_ctl, (uint32_t *)p_seg, (int32_t *)p_log,
-                (uint64_t *)p_key, (uint64_t *)p_R, (uint32_t *)p_fs, (uint32_t *)p_bs,
+                (uint64_t *)p_key, (uint64_t *)p_keyn, (uint64_t *)p_R, (uint32_t *)p_fs, (uint32_t *)p_bs,
                 {(int32_t *)p0, (int32_t *)p1, (int32_t *)p2}, {(int32_t *)u0, (int32_t *)u1}, (int32_t *)c};
     return p_desc && c;
   }
@@ -925,7 +1290,7 @@ int grid_blocks(int driver, int requested, int *blocks) {
 }
 
 // Descriptor of one graph (node offset set by the caller); returns a status.
-int make_desc(const cldiam_graph &x, int g, GDesc *out) {
+int make_desc(const cldiam_graph &x, int g, float bucket_width, GDesc *out) {
   if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 31) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
       !x.d_D || x.params.tau < 1) {
     cld::set_error("decompose: invalid graph %d (n=%d m=%lld tau=%u)", g, x.n, (long long)x.m, x.params.tau);
@@ -943,6 +1308,14 @@ int make_desc(const cldiam_graph &x, int g, GDesc *out) {
   d.K = gamma * x.params.tau * L;
   d.stop = (uint32_t)ceil(8.0 * x.params.tau * L);
   d.seed = x.params.seed;
+  if (x.params.variant > CLDIAM_VARIANT_CLUSTER2) {
+    cld::set_error("decompose: unknown variant %u (graph %d)", x.params.variant, g);
+    return CLDIAM_EINVAL;
+  }
+  d.variant = x.params.variant;
+  d.step_cap = x.params.step_cap;
+  d.c2_iters = 0;
+  while (((int64_t)1 << d.c2_iters) < (int64_t)x.n) d.c2_iters++;   // ceil(log2 n)
   uint64_t d0 = x.params.delta0;
   if (d0 == 0) d0 = x.m > 0 ? x.weight_sum / (uint64_t)x.m : 1;
   if (d0 < 1) d0 = 1;
@@ -951,6 +1324,13 @@ int make_desc(const cldiam_graph &x, int g, GDesc *out) {
     return CLDIAM_EOVERFLOW;
   }
   d.delta0 = (uint32_t)d0;
+  // bucket width in mean arc weights -> distance units (0 = unbounded)
+  if (bucket_width == 0.f) bucket_width = CLDIAM_BUCKET_DEFAULT;
+  d.bucket = 0;
+  if (bucket_width > 0.f && x.m > 0 && d.variant != CLDIAM_VARIANT_STEPS) {
+    const double b = ceil((double)bucket_width * ((double)x.weight_sum / (double)x.m));
+    d.bucket = b >= 4294967295.0 ? 0u : (b < 1.0 ? 1u : (uint32_t)b);
+  }
   return CLDIAM_OK;
 }
 
@@ -966,6 +1346,10 @@ void fill_stats(const GDesc &d, const GState &st, const GCount &cn, const int32_
   o->sweeps = (int32_t)st.sweeps;
   o->radius = cn.radius.v;
   o->status = st.status;
+  o->rounds = st.rounds;
+  o->radius1 = st.radius1;
+  o->updates = st.updates;
+  o->messages = cn.msgs.v;
   for (int s = 0; s < CLDIAM_STAGE_LOG && s < o->stages; ++s) {
     const int32_t *l = log + (size_t)s * 4;
     o->stage_uncovered[s] = l[0];
@@ -1000,7 +1384,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   int64_t N = 0;
   std::vector<GDesc> desc(G);
   for (int g = 0; g < G; ++g) {
-    int rc = make_desc(gs[g], g, &desc[g]);
+    int rc = make_desc(gs[g], g, tuning ? tuning->bucket_width : 0.f, &desc[g]);
     if (rc) return rc;
     desc[g].off = N;
     N += gs[g].n;
@@ -1014,7 +1398,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   }
   Job job{};
   job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
-  job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = G;
   job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
@@ -1136,6 +1520,7 @@ struct cldiam_server {
   Job job;
   int64_t ncap;
   int32_t gcap;
+  float bucket_width;
   hipStream_t stream;
   int blocks;
   std::vector<GDesc> desc;
@@ -1211,11 +1596,12 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   }
   s->ncap = node_capacity;
   s->gcap = max_graphs;
+  s->bucket_width = tuning ? tuning->bucket_width : 0.f;
   s->stream = (hipStream_t)stream;
   Job &job = s->job;
   const Layout &L = s->L;
   job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
-  job.key = L.key; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = max_graphs;
   job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
@@ -1265,7 +1651,7 @@ extern "C" int cldiam_server_submit(cldiam_server *s, const cldiam_graph *g, uin
   if (!s || !g) { cld::set_error("server: null argument"); return CLDIAM_EINVAL; }
   if (g->n > s->ncap) { cld::set_error("server: graph of %d nodes above the capacity %lld", g->n, (long long)s->ncap); return CLDIAM_ENOMEM; }
   cldiam_server::Pending p;
-  int rc = make_desc(*g, 0, &p.d);
+  int rc = make_desc(*g, 0, s->bucket_width, &p.d);
   if (rc) return rc;
   p.tag = tag;
   s->queue.push_back(p);

@@ -70,6 +70,29 @@ def test_road4096_invariants_on_samples(road):
     assert int(d.max()) == st.radius <= sum(st.stage_delta)
 
 
+@pytest.mark.parametrize("variant", ["cluster2", "steps"])
+def test_road4096_variants(road, variant):
+    """CLUSTER2 and the literal step-synchronous variant at full size."""
+    g, counts, dg = road
+    ref = counts[variant]
+    var = cd.VARIANT_CLUSTER2 if variant == "cluster2" else cd.VARIANT_STEPS
+    print(f"[fullsize] {variant}", file=sys.stderr, flush=True)
+    cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"], variant=var)
+    assert (st.stages, st.delta_end, st.num_clusters, st.radius) == \
+        (ref["stages"], ref["delta_end"], ref["num_clusters"], ref["radius"])
+    if variant == "cluster2":
+        assert st.radius1 == ref["radius1"]
+    else:
+        assert (st.levels, st.rounds, st.messages, st.updates) == \
+            (ref["levels"], ref["rounds"], ref["messages"], ref["updates"])
+    assert _digest(cluster.cpu().numpy()) == ref["cluster_sha256"]
+    assert _digest(cd.u64(D)) == ref["D_sha256"]
+    q = cd.cldiam_build_quotient(dg, cluster, D)
+    assert q.k == ref["quotient_k"]
+    phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
+    assert (phi, approx) == (ref["phi_gc"], ref["phi_approx"])
+
+
 @pytest.mark.timeout(900)
 def test_rmat24_decompose_quotient_estimate():
     import torch
