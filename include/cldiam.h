@@ -180,7 +180,8 @@ typedef struct {
 /* Schedule knobs of a decomposition job.  They change only how the work is
  * scheduled on the device, never the results. */
 typedef struct {
-  int32_t local_rounds; /* workgroup-local relaxation rounds per sweep; < 0 = default (4) */
+  int32_t local_rounds; /* workgroup-local relaxation rounds per sweep (16 while a frontier has at most
+                           32768 nodes); < 0 = default (8) */
   int32_t grid_blocks;  /* workgroups per sweep; 0 = one per compute unit */
   float bucket_width;   /* distance bucket of a relaxation sweep, in mean arc weights: a sweep relaxes
                            only frontier nodes whose tentative distance is below (smallest distance on

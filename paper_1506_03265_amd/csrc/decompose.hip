@@ -182,7 +182,9 @@ constexpr int kMidDeg = 32;       // rows above this degree are relaxed by one w
 constexpr int kBigDeg = 8192;     // rows above this degree are relaxed by the whole workgroup
 constexpr int kMidCap = 2048;     // deferred wave rows per round
 constexpr int kBigCap = 128;      // deferred workgroup rows per round
-constexpr int kLocalRounds = 4;   // default local relaxation rounds per RELAX run
+constexpr int kLocalRounds = 8;   // default local relaxation rounds per RELAX run
+constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get kSmallRounds local rounds
+constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 constexpr uint32_t kPassChunk = kThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
 
@@ -1087,7 +1089,12 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     // Every improved node is also on the global next frontier, so these
     // rounds only move the fixpoint closer; dropped overflow loses nothing.
     int q = 0;
-    for (int round = 0; round < job.local_rounds; ++round) {
+    // a small frontier leaves the grid idle between sweeps: let each
+    // workgroup carry its part of the growth further before the next one
+    const uint32_t graph_items = job.seg[2 * job.G + 1 + g];
+    const int rounds = (job.local_rounds > 0 && graph_items <= kSmallFrontier && job.local_rounds < kSmallRounds)
+                           ? kSmallRounds : job.local_rounds;
+    for (int round = 0; round < rounds; ++round) {
       __syncthreads();
       const uint32_t n = S.lq_cnt[q] < kLocalCap ? S.lq_cnt[q] : kLocalCap;
       if (n == 0) break;
