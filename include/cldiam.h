@@ -181,7 +181,8 @@ typedef struct {
  * scheduled on the device, never the results. */
 typedef struct {
   int32_t local_rounds; /* workgroup-local relaxation rounds per sweep (16 while a frontier has at most
-                           32768 nodes); < 0 = default (8) */
+                           32768 nodes); < 0 = default: 8 on graphs with at most 16 arcs per node,
+                           on denser ones 2 above 2^21 nodes and 0 below */
   int32_t grid_blocks;  /* workgroups per sweep; 0 = one per compute unit */
   float bucket_width;   /* distance bucket of a relaxation sweep, in mean arc weights: a sweep relaxes
                            only frontier nodes whose tentative distance is below (smallest distance on

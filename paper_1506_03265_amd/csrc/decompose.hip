@@ -99,7 +99,7 @@ struct GDesc {
   uint32_t variant;  // CLDIAM_VARIANT_*
   uint32_t step_cap; // synchronous steps: most steps per PartialGrowth call (0 = none)
   uint32_t c2_iters; // CLUSTER2: ceil(log2 n) iterations
-  uint32_t pad;
+  int32_t local_rounds;  // workgroup-local relaxation rounds per RELAX run
 };
 
 // Control-owned state of one graph.
@@ -163,7 +163,9 @@ struct Job {
                      // [2G+1, 3G]: items of the graph in this sweep
   int32_t *log;      // G x CLDIAM_STAGE_LOG x 4
   uint64_t *key;
-  uint64_t *keyn;    // synchronous steps: state after the current step (key holds the state before it)
+  uint64_t *keyn;    // synchronous steps: state after the current step (key holds the state before it);
+                     // otherwise, for rows above kMidDeg arcs, the key of the row's last scan
+  uint32_t *slim;    // with keyn: the light limit (Delta - d) of that scan; arcs up to it have been offered
   uint64_t *R;
   uint32_t *fstamp;
   uint32_t *bstamp;
@@ -171,7 +173,6 @@ struct Job {
   int32_t *U[2];
   int32_t *C;
   int32_t G;
-  int32_t local_rounds;   // local relaxation rounds per RELAX run
   int32_t nblocks;        // workgroups of a sweep launch
 };
 
@@ -183,6 +184,9 @@ constexpr int kBigDeg = 8192;     // rows above this degree are relaxed by the w
 constexpr int kMidCap = 2048;     // deferred wave rows per round
 constexpr int kBigCap = 128;      // deferred workgroup rows per round
 constexpr int kLocalRounds = 8;   // default local relaxation rounds per RELAX run
+constexpr int kLocalRoundsDense = 2;   // ... on graphs with more than kDenseDegree arcs per node and
+constexpr int kDenseDegree = 16;       // more than kDenseLarge nodes (none on smaller dense graphs)
+constexpr int32_t kDenseLarge = 1 << 21;
 constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get kSmallRounds local rounds
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
@@ -527,6 +531,8 @@ struct Stage {
   int32_t big[kBigCap];      // rows deferred to the whole workgroup
   uint32_t mid_cnt, big_cnt;
   unsigned long long blk_min;  // workgroup minimum for the NEXT scan of a big row
+  unsigned long long row_key;  // key of the big row being scanned
+  int32_t row_start;           // first arc of its scan
   uint32_t blk_hit;
   uint32_t cnt[3];
   uint32_t base[3];
@@ -775,13 +781,39 @@ __device__ __forceinline__ uint64_t next_small(const Job &job, const GDesc &d, i
   return CLD_INF64;
 }
 
+// Long rows remember their last scan (key and light limit).  Within a Delta
+// level a node's key only decreases and Delta is fixed, so a record with the
+// node's current key means that every arc up to the recorded limit has
+// already been offered with this key; once a level is at its fixpoint the
+// reached nodes' keys are final, so a larger Delta only has to look past the
+// recorded limit; and after a stage the arcs up to it lead to assigned nodes.
+// A record read in a race is never larger than what some scan with an equal
+// or better key has covered, so skipping up to it drops no useful offer.
+__device__ __forceinline__ int32_t resume_at(const Job &job, const GDesc &d, int64_t off, int32_t u, uint64_t ku,
+                                             int32_t a0, int32_t a1) {
+  if (job.keyn[off + u] != ku) return a0;
+  const uint32_t done = job.slim[off + u];
+  int32_t lo = a0, hi = a1;   // first arc with w > done
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint32_t)(d.arcs[mid] >> 32) <= done) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void note_scan(const Job &job, int64_t off, int32_t u, uint64_t ku, uint32_t lim) {
+  job.slim[off + u] = lim;
+  job.keyn[off + u] = ku;
+}
+
 // Cooperative passes over the rows deferred in this round: each wave takes
 // whole mid-size rows (64 arcs per step), then the whole workgroup takes each
 // big row (blockDim arcs per step).  mode 0 relaxes the light prefix; mode 2
 // does the same as a synchronous step; mode 1 (NEXT) finds the first heavy arc
 // into an unreached node and folds d_u + w into S.acc.
 __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint32_t delta, uint32_t it,
-                              uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq, int mode) {
+                              uint32_t level_id, Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq, int mode,
+                              bool resume) {
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const uint32_t nm = S.mid_cnt < kMidCap ? S.mid_cnt : kMidCap;
@@ -793,7 +825,8 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
     const uint64_t ku = job.key[off + u];
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
     if (mode != 1) {
-      for (int32_t base = a0; base < a1; base += 64) {
+      const int32_t start = resume ? resume_at(job, d, off, u, ku, a0, a1) : a0;
+      for (int32_t base = start; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
         const uint64_t arc = a < a1 ? d.arcs[a] : ~0ull;
         const bool light = a < a1 && (uint32_t)(arc >> 32) <= lim;
@@ -805,6 +838,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
         }
       }
       if (lane == 0 && (uint32_t)(d.arcs[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
+      if (resume && lane == 0) note_scan(job, off, u, ku, lim);
     } else {
       for (int32_t base = a0; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
@@ -825,7 +859,11 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   for (uint32_t h = 0; h < nb; ++h) {
     const int32_t u = S.big[h];
     const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
-    const uint64_t ku = job.key[off + u];
+    // one read of u's key for the whole workgroup, so that every thread
+    // scans with the same key and the scan record describes all of them
+    if (threadIdx.x == 0) S.row_key = job.key[off + u];
+    __syncthreads();
+    const uint64_t ku = S.row_key;
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
     int32_t lo = a0, hi = a1;  // first index with w > lim
     while (lo < hi) {
@@ -833,7 +871,10 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       if ((uint32_t)(d.arcs[mid] >> 32) <= lim) lo = mid + 1; else hi = mid;
     }
     if (mode != 1) {
-      for (int32_t a = a0 + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
+      if (threadIdx.x == 0) S.row_start = resume ? resume_at(job, d, off, u, ku, a0, lo) : a0;
+      __syncthreads();
+      const int32_t start = S.row_start;
+      for (int32_t a = start + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
         ++scanned;
         if (mode == 2) relax_one_sync(job, off, ku, d.arcs[a], it, S, out);
         else relax_one(job, off, ku, d.arcs[a], it, S, out, lq_cnt, lq);
@@ -841,6 +882,8 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
       // keep LDS staging within bounds between rows
       __syncthreads();
+      // every thread's part of the row is done: record the scan
+      if (resume && threadIdx.x == 0) note_scan(job, off, u, ku, lim);
       if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
       __syncthreads();
       if (S.flush) stage_flush(S, out, 3);
@@ -945,6 +988,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       break;
   }
   const bool steps = d.variant == CLDIAM_VARIANT_STEPS;
+  const bool resume = !steps && !s.c2;   // long rows resume their last scan (keyn/slim hold scan records)
   if (threadIdx.x == 0) {
     S.acc = (phase == PH_NEXT) ? CLD_INF64 : 0ull;
     S.acc32 = 0;
@@ -966,7 +1010,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           const uint32_t x0 = cld_philox_word0((uint32_t)v, stage, 0u, 0u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
           if ((uint64_t)x0 < T) {
             job.key[off + v] = (uint64_t)(uint32_t)v;
-            job.keyn[off + v] = (uint64_t)(uint32_t)v;
+            if (steps) job.keyn[off + v] = (uint64_t)(uint32_t)v;
             stage_push(S, out, 0, v);
             stage_push(S, out, 1, v);
             atomicAdd(&S.acc32, 1u);
@@ -1075,7 +1119,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     }
     if (phase == PH_RELAX || phase == PH_NEXT)
       scanned += coop_rows(job, d, off, delta, it, level_id, S, out, steps ? nullptr : &S.lq_cnt[0],
-                           steps ? nullptr : S.lq[0], phase == PH_NEXT ? 1 : (steps ? 2 : 0));
+                           steps ? nullptr : S.lq[0], phase == PH_NEXT ? 1 : (steps ? 2 : 0), resume);
     if (nout) {
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -1092,8 +1136,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     // a small frontier leaves the grid idle between sweeps: let each
     // workgroup carry its part of the growth further before the next one
     const uint32_t graph_items = job.seg[2 * job.G + 1 + g];
-    const int rounds = (job.local_rounds > 0 && graph_items <= kSmallFrontier && job.local_rounds < kSmallRounds)
-                           ? kSmallRounds : job.local_rounds;
+    const int rounds = (d.local_rounds > 0 && graph_items <= kSmallFrontier && d.local_rounds < kSmallRounds)
+                           ? kSmallRounds : d.local_rounds;
     for (int round = 0; round < rounds; ++round) {
       __syncthreads();
       const uint32_t n = S.lq_cnt[q] < kLocalCap ? S.lq_cnt[q] : kLocalCap;
@@ -1103,7 +1147,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
         scanned += relax_item(job, d, off, delta, theta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1],
                               S.lq[q ^ 1]);
-      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0);
+      scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0, resume);
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
       __syncthreads();
@@ -1163,6 +1207,7 @@ __global__ void __launch_bounds__(256) k_init(Job job, int64_t total_n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += stride) {
     job.key[i] = CLD_INF64;
     job.keyn[i] = CLD_INF64;
+    job.slim[i] = 0;
     job.R[i] = 0;
     job.fstamp[i] = 0;
     job.bstamp[i] = 0;
@@ -1181,6 +1226,7 @@ __global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     job.key[off + i] = CLD_INF64;
     job.keyn[off + i] = CLD_INF64;
+    job.slim[off + i] = 0;
     job.R[off + i] = 0;
     job.fstamp[off + i] = 0;
     job.bstamp[off + i] = 0;
@@ -1218,7 +1264,7 @@ struct Layout {
   uint32_t *seg;
   int32_t *log;
   uint64_t *key, *keyn, *R;
-  uint32_t *fstamp, *bstamp;
+  uint32_t *slim, *fstamp, *bstamp;
   int32_t *pool[3], *U[2], *C;
 };
 
@@ -1233,6 +1279,7 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto p_key = a.template take<uint64_t>(N);
   auto p_keyn = a.template take<uint64_t>(N);
   auto p_R = a.template take<uint64_t>(N);
+  auto p_slim = a.template take<uint32_t>(N);
   auto p_fs = a.template take<uint32_t>(N);
   auto p_bs = a.template take<uint32_t>(N);
   auto p0 = a.template take<int32_t>(N);
@@ -1243,7 +1290,8 @@ bool carve(A &a, int64_t N, int32_t G, Layout *L) {
   auto c = a.template take<int32_t>(N);
   if (L) {
     *L = Layout{(GDesc *)p_desc, (GState *)p_st, (GCount *)p_cn, (Ctl *)p_ctl, (uint32_t *)p_seg, (int32_t *)p_log,
-                (uint64_t *)p_key, (uint64_t *)p_keyn, (uint64_t *)p_R, (uint32_t *)p_fs, (uint32_t *)p_bs,
+                (uint64_t *)p_key, (uint64_t *)p_keyn, (uint64_t *)p_R, (uint32_t *)p_slim, (uint32_t *)p_fs,
+                (uint32_t *)p_bs,
                 {(int32_t *)p0, (int32_t *)p1, (int32_t *)p2}, {(int32_t *)u0, (int32_t *)u1}, (int32_t *)c};
     return p_desc && c;
   }
@@ -1297,7 +1345,8 @@ int grid_blocks(int driver, int requested, int *blocks) {
 }
 
 // Descriptor of one graph (node offset set by the caller); returns a status.
-int make_desc(const cldiam_graph &x, int g, float bucket_width, GDesc *out) {
+int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *out) {
+  float bucket_width = tuning ? tuning->bucket_width : 0.f;
   if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 31) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
       !x.d_D || x.params.tau < 1) {
     cld::set_error("decompose: invalid graph %d (n=%d m=%lld tau=%u)", g, x.n, (long long)x.m, x.params.tau);
@@ -1321,6 +1370,12 @@ int make_desc(const cldiam_graph &x, int g, float bucket_width, GDesc *out) {
   }
   d.variant = x.params.variant;
   d.step_cap = x.params.step_cap;
+  // local rounds: the caller's, else many on sparse graphs (long growth
+  // paths: each round carries the frontier one more hop without a sweep)
+  // and few on dense ones (their rows are long and their growth shallow)
+  if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
+  else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
+  else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;
   d.c2_iters = 0;
   while (((int64_t)1 << d.c2_iters) < (int64_t)x.n) d.c2_iters++;   // ceil(log2 n)
   uint64_t d0 = x.params.delta0;
@@ -1391,7 +1446,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   int64_t N = 0;
   std::vector<GDesc> desc(G);
   for (int g = 0; g < G; ++g) {
-    int rc = make_desc(gs[g], g, tuning ? tuning->bucket_width : 0.f, &desc[g]);
+    int rc = make_desc(gs[g], g, tuning, &desc[g]);
     if (rc) return rc;
     desc[g].off = N;
     N += gs[g].n;
@@ -1405,11 +1460,10 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   }
   Job job{};
   job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
-  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.slim = L.slim; job.fstamp = L.fstamp;
+  job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = G;
-  job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
-  if (job.local_rounds > 64) job.local_rounds = 64;
 
   CLD_HIP(hipMemcpyAsync(L.desc, desc.data(), sizeof(GDesc) * G, hipMemcpyHostToDevice, stream));
   CLD_HIP(hipMemsetAsync(L.st, 0, sizeof(GState) * G, stream));
@@ -1527,7 +1581,7 @@ struct cldiam_server {
   Job job;
   int64_t ncap;
   int32_t gcap;
-  float bucket_width;
+  cldiam_tuning tuning;
   hipStream_t stream;
   int blocks;
   std::vector<GDesc> desc;
@@ -1603,16 +1657,15 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   }
   s->ncap = node_capacity;
   s->gcap = max_graphs;
-  s->bucket_width = tuning ? tuning->bucket_width : 0.f;
+  s->tuning = tuning ? *tuning : cldiam_tuning{-1, 0, 0.f, 0};
   s->stream = (hipStream_t)stream;
   Job &job = s->job;
   const Layout &L = s->L;
   job.desc = L.desc; job.st = L.st; job.cn = L.cn; job.ctl = L.ctl; job.seg = L.seg; job.log = L.log;
-  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.fstamp = L.fstamp; job.bstamp = L.bstamp;
+  job.key = L.key; job.keyn = L.keyn; job.R = L.R; job.slim = L.slim; job.fstamp = L.fstamp;
+  job.bstamp = L.bstamp;
   for (int i = 0; i < 3; ++i) job.pool[i] = L.pool[i];
   job.U[0] = L.U[0]; job.U[1] = L.U[1]; job.C = L.C; job.G = max_graphs;
-  job.local_rounds = (tuning && tuning->local_rounds >= 0) ? tuning->local_rounds : kLocalRounds;
-  if (job.local_rounds > 64) job.local_rounds = 64;
   int rc = grid_blocks(CLDIAM_DRIVER_HOST, tuning ? tuning->grid_blocks : 0, &s->blocks);
   if (rc) { delete s; return rc; }
   if (s->blocks <= 0) s->blocks = 256;
@@ -1658,7 +1711,7 @@ extern "C" int cldiam_server_submit(cldiam_server *s, const cldiam_graph *g, uin
   if (!s || !g) { cld::set_error("server: null argument"); return CLDIAM_EINVAL; }
   if (g->n > s->ncap) { cld::set_error("server: graph of %d nodes above the capacity %lld", g->n, (long long)s->ncap); return CLDIAM_ENOMEM; }
   cldiam_server::Pending p;
-  int rc = make_desc(*g, 0, s->bucket_width, &p.d);
+  int rc = make_desc(*g, 0, &s->tuning, &p.d);
   if (rc) return rc;
   p.tag = tag;
   s->queue.push_back(p);
