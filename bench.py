@@ -400,17 +400,21 @@ def delta0_bench(args):
 
 def stepcap_bench(args):
     """Growing-step cap O(n / tau) (Section 4): the literal step-synchronous
-    variant with caps of n/tau, n/(16 tau) and n/(256 tau) steps per
-    PartialGrowth call, on a mesh with skewed weights and on R-MAT."""
+    variant with caps of n/tau, n/(16 tau), n/(256 tau) and n/(1024 tau) steps
+    per PartialGrowth call, on a mesh with skewed weights, on R-MAT and on a
+    path (the deepest topology)."""
     import graphgen
     import oracle
     import paper_1506_03265_amd as cd
     out = {}
-    for gname, g in (("bimodal512", graphgen.bimodal_mesh(512, 2)), ("rmat18", graphgen.rmat(18, seed=2))):
+    path = graphgen.grid(1, 1 << 16, 100, 3)   # a path: growth needs as many steps as hops
+    path.name = "path65536"
+    for gname, g in (("bimodal512", graphgen.bimodal_mesh(512, 2)), ("rmat18", graphgen.rmat(18, seed=2)),
+                     ("path65536", path)):
         dg = cd.cldiam_load_csr(g)
         lb = _sssp_lower_bound(cd, dg, oracle.sssp_source(g.n, 1))
         rows = []
-        for div in (0, 1, 16, 256):
+        for div in (0, 1, 16, 256, 1024):
             cap = 0 if div == 0 else max(1, g.n // (args.tau * div))
             st, est, t, td = _pipeline(cd, dg, args.tau, 1, variant=cd.VARIANT_STEPS, step_cap=cap, reps=args.steps)
             rows.append({"step_cap": cap, "ms": round(t * 1e3, 3), "rounds": st.rounds, "messages": st.messages,
