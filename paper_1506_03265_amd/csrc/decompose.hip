@@ -532,6 +532,7 @@ struct Stage {
   uint32_t mid_cnt, big_cnt;
   unsigned long long blk_min;  // workgroup minimum for the NEXT scan of a big row
   unsigned long long row_key;  // key of the big row being scanned
+  int32_t row_lo;              // end of its light prefix
   int32_t row_start;           // first arc of its scan
   uint32_t blk_hit;
   uint32_t cnt[3];
@@ -789,16 +790,39 @@ __device__ __forceinline__ uint64_t next_small(const Job &job, const GDesc &d, i
 // recorded limit; and after a stage the arcs up to it lead to assigned nodes.
 // A record read in a race is never larger than what some scan with an equal
 // or better key has covered, so skipping up to it drops no useful offer.
-__device__ __forceinline__ int32_t resume_at(const Job &job, const GDesc &d, int64_t off, int32_t u, uint64_t ku,
-                                             int32_t a0, int32_t a1) {
-  if (job.keyn[off + u] != ku) return a0;
-  const uint32_t done = job.slim[off + u];
-  int32_t lo = a0, hi = a1;   // first arc with w > done
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if ((uint32_t)(d.arcs[mid] >> 32) <= done) lo = mid + 1; else hi = mid;
+// First arc in [lo, hi) of a weight-sorted row with w > x, found by the 64
+// lanes of a wave together: each round samples 64 evenly spaced arcs and
+// keeps the bracket of the first one above x (two or three dependent loads
+// for rows up to 8192 arcs instead of a dozen for a binary search).  Every
+// lane of the wave calls it with the same arguments and gets the result.
+__device__ __forceinline__ int32_t wave_first_above(const uint64_t *arcs, int32_t lo, int32_t hi, uint32_t x) {
+  const int32_t lane = (int32_t)(threadIdx.x & 63);
+  while (hi - lo > 64) {
+    const int32_t step = (hi - lo + 63) >> 6;
+    const int32_t p = lo + lane * step;
+    const bool above = p < hi && (uint32_t)(arcs[p] >> 32) > x;
+    const unsigned long long m = __ballot(above);
+    if (m == 0) {
+      // every valid sample is <= x: the answer lies after the last one
+      const int32_t last = lo + ((hi - 1 - lo) / step) * step;
+      lo = last + 1;
+    } else {
+      const int32_t f = __ffsll((long long)m) - 1;
+      const int32_t nlo = f == 0 ? lo : lo + (f - 1) * step + 1;
+      hi = lo + f * step;   // the sample at f is above x
+      lo = nlo;
+      if (f == 0) return hi;
+    }
   }
-  return lo;
+  const int32_t p = lo + lane;
+  const unsigned long long m = __ballot(p < hi && (uint32_t)(arcs[p] >> 32) > x);
+  return m ? lo + (__ffsll((long long)m) - 1) : hi;
+}
+
+__device__ __forceinline__ int32_t resume_at_wave(const Job &job, const GDesc &d, int64_t off, int32_t u,
+                                                  uint64_t ku, int32_t a0, int32_t a1) {
+  if (job.keyn[off + u] != ku) return a0;
+  return wave_first_above(d.arcs, a0, a1, job.slim[off + u]);
 }
 
 __device__ __forceinline__ void note_scan(const Job &job, int64_t off, int32_t u, uint64_t ku, uint32_t lim) {
@@ -825,7 +849,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
     const uint64_t ku = job.key[off + u];
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
     if (mode != 1) {
-      const int32_t start = resume ? resume_at(job, d, off, u, ku, a0, a1) : a0;
+      const int32_t start = resume ? resume_at_wave(job, d, off, u, ku, a0, a1) : a0;
       for (int32_t base = start; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
         const uint64_t arc = a < a1 ? d.arcs[a] : ~0ull;
@@ -840,7 +864,8 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       if (lane == 0 && (uint32_t)(d.arcs[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
       if (resume && lane == 0) note_scan(job, off, u, ku, lim);
     } else {
-      for (int32_t base = a0; base < a1; base += 64) {
+      // the heavy arcs start after the light prefix
+      for (int32_t base = wave_first_above(d.arcs, a0, a1, lim); base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
         const uint64_t arc = a < a1 ? d.arcs[a] : 0ull;
         const uint32_t w = (uint32_t)(arc >> 32);
@@ -859,20 +884,24 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   for (uint32_t h = 0; h < nb; ++h) {
     const int32_t u = S.big[h];
     const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
-    // one read of u's key for the whole workgroup, so that every thread
-    // scans with the same key and the scan record describes all of them
-    if (threadIdx.x == 0) S.row_key = job.key[off + u];
+    // wave 0 reads u's key once for the whole workgroup (so every thread scans
+    // with the same key and the scan record describes all of them) and finds
+    // the end of the light prefix and the resume point
+    if (threadIdx.x < 64) {
+      const uint64_t k = job.key[off + u];
+      const int32_t light_end = wave_first_above(d.arcs, a0, a1, delta - (uint32_t)(k >> 32));
+      const int32_t from = (mode != 1 && resume) ? resume_at_wave(job, d, off, u, k, a0, light_end) : a0;
+      if (threadIdx.x == 0) {
+        S.row_key = k;
+        S.row_lo = light_end;
+        S.row_start = from;
+      }
+    }
     __syncthreads();
     const uint64_t ku = S.row_key;
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
-    int32_t lo = a0, hi = a1;  // first index with w > lim
-    while (lo < hi) {
-      const int32_t mid = lo + ((hi - lo) >> 1);
-      if ((uint32_t)(d.arcs[mid] >> 32) <= lim) lo = mid + 1; else hi = mid;
-    }
+    const int32_t lo = S.row_lo;   // first index with w > lim
     if (mode != 1) {
-      if (threadIdx.x == 0) S.row_start = resume ? resume_at(job, d, off, u, ku, a0, lo) : a0;
-      __syncthreads();
       const int32_t start = S.row_start;
       for (int32_t a = start + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
         ++scanned;
