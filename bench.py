@@ -32,6 +32,7 @@ Other workloads (each prints its own JSON line):
                       CLUSTER2 on the road-like mesh
   --workload delta0   the initial-Delta experiment on a bimodal-weight mesh
   --workload stepcap  the growing-step cap on skewed graphs
+  --workload ceilings random-access ceilings of the GPU (PyTorch kernels)
 
 Only one GPU is supported.
 """
@@ -134,14 +135,31 @@ def step_bench(args, name):
                "sample": f"the full workload once (decompose + quotient + estimate, {tc:.1f} s single-threaded, "
                          f"host {os.cpu_count()} cpus visible)"}
 
+    import hashlib
+    src_sha = hashlib.sha256(open(os.path.join(HERE, "paper_1506_03265_amd", "csrc", "decompose.hip"),
+                                  "rb").read()).hexdigest()
     traffic = None
     tpath = os.path.join(HERE, "profiles", f"{name}_traffic.json")
     if os.path.exists(tpath):
-        import hashlib
         tr = json.load(open(tpath))
-        src = open(os.path.join(HERE, "paper_1506_03265_amd", "csrc", "decompose.hip"), "rb").read()
-        if tr.get("source_sha256") == hashlib.sha256(src).hexdigest():
+        if tr.get("source_sha256") == src_sha:
             traffic = tr["traffic_bytes"]   # counters taken on this very kernel source
+    # random-access view: request counts of one decomposition (counters taken on
+    # this kernel source) against the GPU's scattered-access ceilings
+    random_access = None
+    rpath = os.path.join(HERE, "profiles", f"{name}_requests.json")
+    cpath = os.path.join(HERE, "profiles", "ceilings_bench.json")
+    if os.path.exists(rpath) and os.path.exists(cpath):
+        rq = json.load(open(rpath))
+        ce = json.load(open(cpath))["config"]
+        if rq.get("source_sha256") == src_sha:
+            atom = rq["atomic_with_return"] + rq["atomic_without_return"]
+            floor_s = atom / (ce["random_scatter_min_Gops"] * 1e9) + rq["read_requests"] / (ce["random_gather_Gops"] * 1e9)
+            random_access = {"atomics": atom, "reads": rq["read_requests"], "writes": rq["write_requests"],
+                             "atomics_per_s": round(atom / (kernel_ms / 1e3), 0),
+                             "atomic_ceiling_per_s": ce["random_scatter_min_Gops"] * 1e9,
+                             "gather_ceiling_per_s": ce["random_gather_Gops"] * 1e9,
+                             "floor_ms": round(floor_s * 1e3, 3), "frac": round(floor_s * 1e3 / kernel_ms, 4)}
 
     return {
         "metric": METRIC,
@@ -170,7 +188,7 @@ def step_bench(args, name):
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "kernel": ("k_sweep+k_control launch loop" if st.grid_blocks == 0 else "k_persistent")
                                + " (one decomposition)", "kernel_ms": round(kernel_ms, 4),
-                     "algorithmic_bytes": counts["bytes_decompose"]},
+                     "algorithmic_bytes": counts["bytes_decompose"], "random_access": random_access},
         "cpu_baseline": cpu,
     }
 
@@ -432,6 +450,49 @@ def stepcap_bench(args):
     }
 
 
+def ceilings_bench(args):
+    """Random-access ceilings of the GPU with plain PyTorch kernels: a
+    streaming copy, random 8-byte gathers, and random 64-bit scatter-min
+    (atomic) over a 134 MB array, the size of the road mesh's key array.
+    These bound a relaxation engine whose work is one random gather per arc
+    and one or two random atomics per improvement."""
+    import torch
+    n, ops = 1 << 24, 1 << 26
+    a = torch.full((n,), 1 << 62, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    idx = torch.randint(0, n, (ops,), device="cuda", generator=g)
+    vals = torch.randint(0, 1 << 40, (ops,), device="cuda", dtype=torch.int64, generator=g)
+    out = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t = timed(lambda: b.copy_(a))
+    out["copy_GBps"] = round(2 * n * 8 / t / 1e9, 1)
+    t = timed(lambda: a.index_select(0, idx))
+    out["random_gather_Gops"] = round(ops / t / 1e9, 2)
+    t = timed(lambda: a.scatter_reduce_(0, idx, vals, reduce="amin"))
+    out["random_scatter_min_Gops"] = round(ops / t / 1e9, 2)
+    srt = torch.sort(idx).values
+    t = timed(lambda: a.index_select(0, srt))
+    out["sorted_gather_Gops"] = round(ops / t / 1e9, 2)
+    log(f"[bench] ceilings {out}")
+    return {
+        "metric": "random-access ceilings (streaming copy GB/s, random gathers and random 64-bit atomic min per s)",
+        "value": out["random_scatter_min_Gops"], "unit": "Gatomics/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic", "config": {"workload": f"{n} int64 array (134 MB), {ops} random indices", **out},
+    }
+
+
 def sssp_bench(args):
     import torch
 
@@ -487,7 +548,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="road4096",
-                    choices=["road4096", "rmat24", "rgg256", "serve", "sssp", "variants", "delta0", "stepcap"])
+                    choices=["road4096", "rmat24", "rgg256", "serve", "sssp", "variants", "delta0", "stepcap",
+                             "ceilings"])
     ap.add_argument("--side", type=int, default=2048, help="delta0: mesh side")
     ap.add_argument("--tau", type=int, default=4, help="delta0 / stepcap: tau")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -534,6 +596,8 @@ def main():
         out = delta0_bench(args)
     elif args.workload == "stepcap":
         out = stepcap_bench(args)
+    elif args.workload == "ceilings":
+        out = ceilings_bench(args)
     else:
         out = serve_bench(args)
     print(json.dumps(out), flush=True)
