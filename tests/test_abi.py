@@ -60,3 +60,37 @@ def test_invalid_arguments_fail_before_touching_a_device(lib):
     assert lib.cldiam_build_quotient(0, 0, None, None, None, None, None, None, None, None, None, None, None, 0,
                                      None) == cd.CLDIAM_EINVAL
     assert lib.cldiam_sssp_delta_stepping(10, 0, None, None, 0, 1, None, None, None, 0, None) == cd.CLDIAM_EINVAL
+
+
+def test_python_structures_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structures have the C compiler's
+    sizes and field offsets (a plain C program including cldiam.h prints them)."""
+    import ctypes
+    import subprocess
+    fields = {
+        "cldiam_csr": (cd._Csr, ["n", "m", "d_row_ptr", "d_col", "d_w"]),
+        "cldiam_params": (cd._Params, ["tau", "delta0", "seed", "variant", "step_cap"]),
+        "cldiam_tuning": (cd._Tuning, ["local_rounds", "grid_blocks", "bucket_width"]),
+        "cldiam_graph": (cd._Graph, ["m", "d_arcs", "weight_sum", "params", "d_cluster", "d_D"]),
+        "cldiam_stats": (cd._Stats, ["stages", "radius", "arcs_scanned", "status", "kernel_ms", "iterations",
+                                     "rounds", "messages", "updates", "radius1", "stage_uncovered",
+                                     "stage_delta"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cldiam.h"', "int main(void) {"]
+    for cname, (_, names) in fields.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in names or []:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        parts = line.split()
+        got[(parts[0], parts[1])] = int(parts[2])
+    for cname, (py, names) in fields.items():
+        assert ctypes.sizeof(py) == got[(cname, "size")], cname
+        for f in names or []:
+            assert getattr(py, f).offset == got[(cname, f)], (cname, f)
