@@ -188,9 +188,14 @@ typedef struct {
                            only frontier nodes whose tentative distance is below (smallest distance on
                            the frontier) + width, and keeps the others for later sweeps of the same
                            growth; 0 = default (CLDIAM_BUCKET_DEFAULT), < 0 = no bucket */
-  int32_t reserved;     /* 0 */
+  int32_t row_bucket_shift; /* nodes whose rows hold more than 32 arcs are relaxed only once their
+                           tentative distance is below (smallest distance on the frontier) +
+                           Delta / 2^shift, so that long rows are rarely scanned twice in one growth;
+                           0 = default (CLDIAM_ROW_SHIFT_DEFAULT), < 0 = no such bucket; values above
+                           31 act as 31.  Synchronous steps use none. */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
+#define CLDIAM_ROW_SHIFT_DEFAULT 8
 
 /* One graph description of a batch (graph operand in DEVICE memory). */
 typedef struct {

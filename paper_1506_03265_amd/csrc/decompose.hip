@@ -100,6 +100,7 @@ struct GDesc {
   uint32_t step_cap; // synchronous steps: most steps per PartialGrowth call (0 = none)
   uint32_t c2_iters; // CLUSTER2: ceil(log2 n) iterations
   int32_t local_rounds;  // workgroup-local relaxation rounds per RELAX run
+  int32_t row_shift;     // long rows use a bucket of width Delta >> row_shift; < 0 = none
 };
 
 // Control-owned state of one graph.
@@ -111,6 +112,7 @@ struct GState {
   int32_t status;
   uint32_t levels, sweeps, centers_total, singletons;
   uint32_t theta;    // RELAX sweeps relax frontier nodes with tentative distance below theta
+  uint32_t row_base; // ... and nodes of long rows only below row_limit(row_base)
   // synchronous steps
   uint32_t steps_call;  // steps of the current PartialGrowth call
   uint32_t fid;         // sweep id that stamped the current active list
@@ -236,6 +238,17 @@ __device__ __forceinline__ uint32_t bucket_limit(const GDesc &d, uint32_t lo) {
   return t < 0xffffffffull ? (uint32_t)t : 0xffffffffu;
 }
 
+// Upper end (exclusive) of the narrower bucket of rows of more than kMidDeg
+// arcs.  Relaxing such a row before its node's distance is nearly final
+// costs a full rescan when the distance drops again, so these rows wait
+// until the frontier minimum comes within Delta / 2^row_shift of them.
+__device__ __forceinline__ uint32_t row_limit(const GDesc &d, uint32_t delta, uint32_t lo) {
+  if (d.row_shift < 0 || lo == 0xffffffffu) return 0xffffffffu;
+  const uint32_t w = delta >> d.row_shift;
+  const uint64_t t = (uint64_t)lo + (w ? w : 1u);
+  return t < 0xffffffffull ? (uint32_t)t : 0xffffffffu;
+}
+
 // CLUSTER2: iteration s.stage + 1 draws centers with probability 2^i / n.
 __device__ void c2_begin_iteration(const GDesc &d, GState &s, GCount &c) {
   const int i = (int)s.stage + 1;
@@ -252,6 +265,7 @@ __device__ __forceinline__ void begin_call(GState &s, uint32_t sweep_id) {
   s.level_id = sweep_id;
   s.steps_call = 0;
   s.theta = 0xffffffffu;
+  s.row_base = 0xffffffffu;
   s.phase = PH_RELAX;
 }
 
@@ -301,6 +315,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       s.level_id = sweep_id;
       s.levels++;
       s.theta = bucket_limit(d, 0);
+      s.row_base = 0;
       c.fmin.v = 0xffffffffu;
       s.phase = PH_RELAX;
       break;
@@ -319,6 +334,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         // the next bucket starts at the smallest distance on the frontier
         const uint32_t th = c.fmin.v == 0xffffffffu ? 0xffffffffu : bucket_limit(d, c.fmin.v);
         if (th > s.theta) s.theta = th;
+        if (c.fmin.v > s.row_base) s.row_base = c.fmin.v;
         c.fmin.v = 0xffffffffu;
       } else {
         c.cnt[s.fcur].v = 0;
@@ -374,6 +390,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         c.cnt[s.blk].v = 0;
         s.level_id = sweep_id;
         s.theta = bucket_limit(d, (uint32_t)c.next.v);
+        s.row_base = (uint32_t)c.next.v;
         c.fmin.v = 0xffffffffu;
         s.phase = PH_RELAX;
       }
@@ -448,6 +465,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       c.cnt[s.blk].v = 0;
       s.level_id = sweep_id;
       s.theta = bucket_limit(d, 0);
+      s.row_base = 0;
       c.fmin.v = 0xffffffffu;
       s.phase = PH_RELAX;
       break;
@@ -616,10 +634,18 @@ __device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v
 }
 
 __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
-                                               uint32_t theta, uint32_t it, uint32_t level_id, int32_t u,
+                                               uint32_t theta, uint32_t theta_row, uint32_t it,
+                                               uint32_t level_id, int32_t u,
                                                Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
   const uint64_t ku = job.key[off + u];
-  if ((uint32_t)(ku >> 32) >= theta) {
+  int32_t a0 = 0, a1 = 0;
+  bool later = (uint32_t)(ku >> 32) >= theta;
+  if (!later) {
+    a0 = d.row_ptr[u];
+    a1 = d.row_ptr[u + 1];
+    later = a1 - a0 > kMidDeg && (uint32_t)(ku >> 32) >= theta_row;
+  }
+  if (later) {
     // beyond the current distance bucket: stays on the frontier for a later
     // sweep (it may already be there if it improved in this sweep)
     if (atomicExch(&job.fstamp[off + u], it) != it) {
@@ -628,8 +654,6 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
     }
     return 0;
   }
-  const int32_t a0 = d.row_ptr[u];
-  const int32_t a1 = d.row_ptr[u + 1];
   if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
@@ -983,6 +1007,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   const int64_t off = d.off;
   const uint32_t phase = s.phase;
   const uint32_t delta = s.delta, level_id = s.level_id, stage = s.stage, ucur = s.ucur, theta = s.theta;
+  const uint32_t row_lim = row_limit(d, delta, s.row_base);
+  const uint32_t theta_row = row_lim < theta ? row_lim : theta;
   const uint32_t fcur = s.fcur, fnxt = s.fnxt, blk = s.blk;
   const uint64_t T = s.T;
   Out out[3];
@@ -1050,8 +1076,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           if (steps)
             scanned += relax_sync(job, d, off, delta, it, level_id, job.pool[fcur][off + idx], S, out);
           else
-            scanned += relax_item(job, d, off, delta, theta, it, level_id, job.pool[fcur][off + idx], S, out,
-                                  &S.lq_cnt[0], S.lq[0]);
+            scanned += relax_item(job, d, off, delta, theta, theta_row, it, level_id, job.pool[fcur][off + idx], S,
+                                  out, &S.lq_cnt[0], S.lq[0]);
           break;
         case PH_COMMIT: {
           const int32_t v = job.pool[fnxt][off + idx];
@@ -1174,8 +1200,8 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       if (threadIdx.x == 0) S.lq_cnt[q ^ 1] = 0;
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
-        scanned += relax_item(job, d, off, delta, theta, it, level_id, S.lq[q][t], S, out, &S.lq_cnt[q ^ 1],
-                              S.lq[q ^ 1]);
+        scanned += relax_item(job, d, off, delta, theta, theta_row, it, level_id, S.lq[q][t], S, out,
+                              &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
       scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0, resume);
       __syncthreads();
       if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
@@ -1402,6 +1428,10 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
   // local rounds: the caller's, else many on sparse graphs (long growth
   // paths: each round carries the frontier one more hop without a sweep)
   // and few on dense ones (their rows are long and their growth shallow)
+  // long-row bucket: the caller's shift, else the default; none for
+  // synchronous steps (their sweeps take every active node)
+  const int32_t rs = tuning ? tuning->row_bucket_shift : 0;
+  d.row_shift = (rs < 0 || d.variant == CLDIAM_VARIANT_STEPS) ? -1 : (rs == 0 ? CLDIAM_ROW_SHIFT_DEFAULT : (rs > 31 ? 31 : rs));
   if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
   else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
   else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;

@@ -39,6 +39,23 @@ def test_schedule_knobs_do_not_change_results(local_rounds, grid_blocks, driver)
     assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
 
 
+@pytest.mark.parametrize("bucket_width,row_shift,variant", [(0.0, 0, 0), (0.0, 1, 0), (0.0, 31, 0), (0.0, -1, 0),
+                                                            (-1.0, 0, 0), (4.0, 3, 0), (1.0, 12, 0), (0.0, 1, 2),
+                                                            (-1.0, 2, 2)])
+def test_bucket_knobs_on_long_rows(bucket_width, row_shift, variant):
+    """Distance buckets (all nodes, and the narrower one of long rows) only
+    reorder relaxations: an R-MAT graph with hub rows of thousands of arcs
+    gives the oracle's outputs at every width, for CLUSTER and CLUSTER2."""
+    g = graphgen.rmat(14, seed=3)
+    _say(f"[systems] buckets width={bucket_width} row_shift={row_shift} variant={variant}")
+    ref = oracle.decompose_cluster2(g, 1, 4) if variant == cd.VARIANT_CLUSTER2 else oracle.decompose(g, 1, 4)
+    dg = cd.cldiam_load_csr(g)
+    c, D, st = cd.cldiam_decompose(dg, 1, 4, variant=variant, bucket_width=bucket_width, row_bucket_shift=row_shift)
+    assert np.array_equal(c.cpu().numpy(), ref.cluster)
+    assert np.array_equal(cd.u64(D), ref.D)
+    assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
+
+
 def test_batch_of_geometric_graphs_matches_oracle():
     sizes = [1000, 1500, 2500, 4000, 7000, 12000, 20000, 30000] * 3
     graphs = [graphgen.rgg(n, i, 5) for i, n in enumerate(sizes)]
