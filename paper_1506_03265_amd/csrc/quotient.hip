@@ -30,12 +30,32 @@ struct QCtl {
   uint32_t k;
   uint32_t pairs;   // emitted arcs
   uint32_t uniq;    // quotient arcs
-  uint32_t pad;
+  uint32_t wide;    // some D does not fit the packed node word
 };
 
 __global__ void k_center_flags(const int32_t *cluster, int32_t n, uint32_t *flag) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     flag[v] = cluster[v] == (int32_t)v ? 1u : 0u;
+}
+
+__device__ __forceinline__ int bits_for_dev(uint32_t x) {  // bits needed for values 0..x, at least 1
+  return x ? 32 - __clz(x) : 1;
+}
+
+// Node word of the packed emission: the dense cluster index in the top kb
+// bits (kb = bits of k-1, k counted by the scan), D in the low 64 - kb bits,
+// so that an arc's far end costs one 8-byte gather instead of three.  A D
+// that does not fit sets ctl->wide, and the emission then reads the plain
+// arrays instead.
+__global__ void k_pack_nodes(const int32_t *cluster, const uint64_t *D, const uint32_t *dense, int32_t n,
+                             QCtl *ctl, uint64_t *pk) {
+  const uint32_t k = ctl->k;
+  const int lb = 64 - bits_for_dev(k > 0 ? k - 1 : 0u);
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t d = D[v];
+    if (d >> lb) ctl->wide = 1u;
+    pk[v] = ((uint64_t)dense[cluster[v]] << lb) | d;
+  }
 }
 
 __global__ void k_center_list(const int32_t *cluster, int32_t n, const uint32_t *dense, int32_t *qcenter) {
@@ -110,18 +130,50 @@ __device__ void hash_flush(EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *c
   __syncthreads();
 }
 
-__device__ __forceinline__ void emit_arc(uint64_t arc, int32_t cu, uint64_t du, uint64_t ka, const int32_t *cluster,
-                                         const uint64_t *D, const uint32_t *dense, EmitState &E, uint64_t *keys,
-                                         uint64_t *vals, QCtl *ctl) {
-  const int32_t v = (int32_t)(uint32_t)arc;
-  const int32_t cv = cluster[v];
-  if (cv != cu) emit_pair(E, ka | (uint64_t)dense[cv], (arc >> 32) + du + D[v], keys, vals, ctl);
+// Node-side inputs of the emission: either cluster ids, D and the dense
+// numbering, or the packed words of k_pack_nodes.
+struct NodeIn {
+  const int32_t *cluster;
+  const uint64_t *D;
+  const uint32_t *dense;
+  const uint64_t *pk;
+  int lb;
+};
+
+// Cluster tag (cluster id, or dense index when packed), D and the key's
+// high part of node u.
+template <bool kPacked>
+__device__ __forceinline__ void node_of(const NodeIn &in, int32_t u, int kb, uint32_t *cu, uint64_t *du,
+                                        uint64_t *ka) {
+  if (kPacked) {
+    const uint64_t x = in.pk[u];
+    *cu = (uint32_t)(x >> in.lb);
+    *du = x & ((1ull << in.lb) - 1ull);
+    *ka = (uint64_t)*cu << kb;
+  } else {
+    *cu = (uint32_t)in.cluster[u];
+    *du = in.D[u];
+    *ka = (uint64_t)in.dense[*cu] << kb;
+  }
 }
 
-__global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n,
-                                                       const int32_t *cluster, const uint64_t *D,
-                                                       const uint32_t *dense, int kb, uint64_t *keys, uint64_t *vals,
-                                                       QCtl *ctl) {
+template <bool kPacked>
+__device__ __forceinline__ void emit_arc(uint64_t arc, uint32_t cu, uint64_t du, uint64_t ka, const NodeIn &in,
+                                         EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
+  const int32_t v = (int32_t)(uint32_t)arc;
+  if (kPacked) {
+    const uint64_t x = in.pk[v];
+    const uint32_t cv = (uint32_t)(x >> in.lb);
+    if (cv != cu) emit_pair(E, ka | (uint64_t)cv, (arc >> 32) + du + (x & ((1ull << in.lb) - 1ull)), keys, vals, ctl);
+  } else {
+    const int32_t cv = in.cluster[v];
+    if ((uint32_t)cv != cu) emit_pair(E, ka | (uint64_t)in.dense[cv], (arc >> 32) + du + in.D[v], keys, vals, ctl);
+  }
+}
+
+template <bool kPacked>
+__global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n, NodeIn in,
+                                                       int kb, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
   __shared__ EmitState E;
   for (uint32_t i = threadIdx.x; i < kHashCap; i += blockDim.x) { E.hkey[i] = ~0ull; E.hval[i] = ~0ull; }
   if (threadIdx.x == 0) { E.nmid = 0; E.nbig = 0; E.used = 0; }
@@ -143,10 +195,10 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const 
         if (slot < kEmitDefer) { lst[slot] = (int32_t)u; done = true; }
       }
       if (!done) {
-        const int32_t cu = cluster[u];
-        const uint64_t du = D[u];
-        const uint64_t ka = (uint64_t)dense[cu] << kb;
-        for (int32_t a = a0; a < a1; ++a) emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+        uint32_t cu;
+        uint64_t du, ka;
+        node_of<kPacked>(in, (int32_t)u, kb, &cu, &du, &ka);
+        for (int32_t a = a0; a < a1; ++a) emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
       }
     }
     __syncthreads();
@@ -154,21 +206,21 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const 
     for (uint32_t i = wave; i < nm; i += nwaves) {
       const int32_t u = E.mid[i];
       const int32_t a0 = rp[u], a1 = rp[u + 1];
-      const int32_t cu = cluster[u];
-      const uint64_t du = D[u];
-      const uint64_t ka = (uint64_t)dense[cu] << kb;
+      uint32_t cu;
+      uint64_t du, ka;
+      node_of<kPacked>(in, u, kb, &cu, &du, &ka);
       for (int32_t a = a0 + (int32_t)lane; a < a1; a += 64)
-        emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+        emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
     }
     const uint32_t nbg = E.nbig < kEmitDefer ? E.nbig : kEmitDefer;
     for (uint32_t i = 0; i < nbg; ++i) {
       const int32_t u = E.big[i];
       const int32_t a0 = rp[u], a1 = rp[u + 1];
-      const int32_t cu = cluster[u];
-      const uint64_t du = D[u];
-      const uint64_t ka = (uint64_t)dense[cu] << kb;
+      uint32_t cu;
+      uint64_t du, ka;
+      node_of<kPacked>(in, u, kb, &cu, &du, &ka);
       for (int32_t a = a0 + (int32_t)threadIdx.x; a < a1; a += (int32_t)blockDim.x)
-        emit_arc(arcs[a], cu, du, ka, cluster, D, dense, E, keys, vals, ctl);
+        emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
       __syncthreads();
       if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
     }
@@ -237,9 +289,9 @@ constexpr int kEmitBlocks = 2048;
 
 template <class A>
 void carve(A &a, int32_t n, int64_t m, uint32_t **flag, uint32_t **dense, QCtl **ctl, uint64_t **keys,
-           uint64_t **vals, uint64_t **ktmp, uint64_t **vtmp, uint32_t **head, uint32_t **idx, uint32_t **emitc) {
+           uint64_t **vals, uint64_t **ktmp, uint64_t **vtmp, uint32_t **head, uint32_t **idx, uint64_t **pk) {
   *ctl = a.template take<QCtl>(1);
-  *emitc = nullptr;
+  *pk = a.template take<uint64_t>((size_t)n);
   *flag = a.template take<uint32_t>((size_t)n);
   *dense = a.template take<uint32_t>((size_t)n);
   *keys = a.template take<uint64_t>((size_t)m + 1);
@@ -264,8 +316,8 @@ extern "C" size_t cldiam_quotient_workspace_size(int32_t n, int64_t m) {
   uint32_t *f, *d, *h, *x;
   QCtl *c;
   uint64_t *k, *v, *kt, *vt;
-  uint32_t *ec;
-  carve(s, n, m, &f, &d, &c, &k, &v, &kt, &vt, &h, &x, &ec);
+  uint64_t *pk;
+  carve(s, n, m, &f, &d, &c, &k, &v, &kt, &vt, &h, &x, &pk);
   size_t extra = cld::radix_ws_bytes(m + 1);
   size_t sc = cld::scan_ws_bytes((int64_t)n > m + 1 ? (int64_t)n : m + 1);
   return s.s.used + (extra > sc ? extra : sc);
@@ -285,8 +337,8 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   uint32_t *flag, *dense, *head, *idx;
   QCtl *ctl;
   uint64_t *keys, *vals, *ktmp, *vtmp;
-  uint32_t *emitc;
-  carve(a, n, m, &flag, &dense, &ctl, &keys, &vals, &ktmp, &vtmp, &head, &idx, &emitc);
+  uint64_t *pk;
+  carve(a, n, m, &flag, &dense, &ctl, &keys, &vals, &ktmp, &vtmp, &head, &idx, &pk);
   if (!idx || a.used > ws_bytes) {
     cld::set_error("build_quotient: workspace of %zu bytes, %zu needed", ws_bytes, cldiam_quotient_workspace_size(n, m));
     return CLDIAM_ENOMEM;
@@ -300,6 +352,10 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   if (rc) return rc;
   k_center_list<<<cld::blocks_for(n, kT, 8192), kT, 0, stream>>>(d_cluster, n, dense, d_qcenter);
   CLD_LAUNCH_CHECK("k_center_list");
+  if (m > 0) {
+    k_pack_nodes<<<cld::blocks_for(n, kT, 8192), kT, 0, stream>>>(d_cluster, d_D, dense, n, ctl, pk);
+    CLD_LAUNCH_CHECK("k_pack_nodes");
+  }
   QCtl h;
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
@@ -307,7 +363,12 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   const int kb = bits_for(k > 0 ? (uint32_t)(k - 1) : 0u);
   if (m > 0) {
     const unsigned eb = (unsigned)(n < kEmitBlocks * 64 ? (n + 63) / 64 : kEmitBlocks);
-    k_emit<<<eb, kEmitThreads, 0, stream>>>(d_row_ptr, d_arcs, n, d_cluster, d_D, dense, kb, keys, vals, ctl);
+    NodeIn in{d_cluster, d_D, dense, pk, 64 - kb};
+    if (!h.wide) {   // every D fits beside the cluster index
+      k_emit<true><<<eb, kEmitThreads, 0, stream>>>(d_row_ptr, d_arcs, n, in, kb, keys, vals, ctl);
+    } else {
+      k_emit<false><<<eb, kEmitThreads, 0, stream>>>(d_row_ptr, d_arcs, n, in, kb, keys, vals, ctl);
+    }
     CLD_LAUNCH_CHECK("k_emit");
   }
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));

@@ -291,3 +291,31 @@ def test_quotient_with_many_clusters(name, maker, tau):
     assert np.array_equal(q.row_ptr.cpu().numpy(), rrp)
     assert np.array_equal(q.col.cpu().numpy(), rcol)
     assert np.array_equal(cd.u64(q.w), rw)
+
+
+@pytest.mark.parametrize("extra", [0, -1, 1], ids=["small", "widest_packed", "wide"])
+def test_quotient_with_large_distance_bounds(extra):
+    """The quotient takes any D: with the largest D one below, at, or past the
+    width left beside the cluster index in the packed node word, both emission
+    paths give the oracle's G_C (weights w + D_u + D_v in 64 bits)."""
+    import torch
+    g = graphgen.rmat(12, seed=8)
+    ref = oracle.decompose(g, 2, 5)
+    k = int(ref.num_clusters)
+    kb = max(1, int(k - 1).bit_length())
+    D = ref.D.copy()
+    if extra:
+        D[7] = np.uint64((1 << (64 - kb)) - 1 if extra < 0 else 1 << (64 - kb))
+    _say(f"[parity] quotient large D k={k} kb={kb} D[7]={int(D[7])}")
+    dec = oracle.Decomposition(ref.cluster, D, ref.stages, ref.levels, ref.delta0, ref.delta_end, ref.stop,
+                               ref.num_clusters, ref.singletons, ref.radius)
+    dg = cd.cldiam_load_csr(g)
+    cl = torch.from_numpy(ref.cluster.astype(np.int32)).cuda()
+    Dt = torch.from_numpy(D.view(np.int64)).cuda()
+    q = cd.cldiam_build_quotient(dg, cl, Dt)
+    rq = oracle.quotient(g, dec)
+    rrp, rcol, rw = rq.csr()
+    assert q.k == rq.k == k
+    assert np.array_equal(q.row_ptr.cpu().numpy(), rrp)
+    assert np.array_equal(q.col.cpu().numpy(), rcol)
+    assert np.array_equal(cd.u64(q.w), rw)
