@@ -193,6 +193,9 @@ typedef struct {
                            Delta / 2^shift, so that long rows are rarely scanned twice in one growth;
                            0 = default (CLDIAM_ROW_SHIFT_DEFAULT), < 0 = no such bucket; values above
                            31 act as 31.  Synchronous steps use none. */
+  int32_t chunk_factor; /* chunks of a growth sweep per workgroup: the first goes to each workgroup, the
+                           rest to whichever workgroup is free next; 0 = default (3 on graphs of more
+                           than 2^21 nodes with more than 16 arcs per node, else 1), at most 64 */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
 #define CLDIAM_ROW_SHIFT_DEFAULT 8

@@ -101,6 +101,7 @@ struct GDesc {
   uint32_t c2_iters; // CLUSTER2: ceil(log2 n) iterations
   int32_t local_rounds;  // workgroup-local relaxation rounds per RELAX run
   int32_t row_shift;     // long rows use a bucket of width Delta >> row_shift; < 0 = none
+  int32_t chunk_factor;  // RELAX / NEXT chunks per workgroup and sweep
 };
 
 // Control-owned state of one graph.
@@ -153,6 +154,7 @@ struct Ctl {
   unsigned long long t_start;   // wall clock at the first control step
   unsigned long long t_limit;   // ticks after which the job stops with a timeout
   PadU64 arcs;                  // arcs read by relaxation (diagnostic)
+  PadU32 cursor;                // chunks of the current sweep taken beyond the first nblocks
   CldBarrier bar;
 };
 
@@ -189,6 +191,7 @@ constexpr int kLocalRounds = 8;   // default local relaxation rounds per RELAX r
 constexpr int kLocalRoundsDense = 2;   // ... on graphs with more than kDenseDegree arcs per node and
 constexpr int kDenseDegree = 16;       // more than kDenseLarge nodes (none on smaller dense graphs)
 constexpr int32_t kDenseLarge = 1 << 21;
+constexpr int32_t kDenseChunks = 3;     // RELAX / NEXT chunks per workgroup on dense graphs
 constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get kSmallRounds local rounds
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
@@ -501,14 +504,16 @@ __device__ void control_block(const Job &job) {
       const uint32_t phase = job.st[g].phase;
       const uint32_t n_items =
           job.st[g].phase == PH_C2_INIT ? (uint32_t)job.desc[g].n : items_of(job.st[g], job.cn[g]);
-      // Every graph is cut into its own chunks, at most one per workgroup, so
-      // that the frontier of each graph is spread over the whole grid whatever
-      // the other graphs of the job are doing (a node pass of millions of
-      // cheap items beside a small frontier of costly rows).
+      // Every graph is cut into its own chunks, at most chunk_factor per
+      // workgroup, so that the frontier of each graph is spread over the whole
+      // grid whatever the other graphs of the job are doing (a node pass of
+      // millions of cheap items beside a small frontier of costly rows).
       uint32_t per = 0;
       if (n_items) {
-        per = (n_items + (uint32_t)job.nblocks - 1) / (uint32_t)job.nblocks;
-        if (phase != PH_RELAX && phase != PH_NEXT && per < kPassChunk) per = kPassChunk;
+        const bool grow = phase == PH_RELAX || phase == PH_NEXT;
+        const uint32_t nch = (uint32_t)job.nblocks * (grow ? (uint32_t)job.desc[g].chunk_factor : 1u);
+        per = (n_items + nch - 1) / nch;
+        if (!grow && per < kPassChunk) per = kPassChunk;
         items = (n_items + per - 1) / per;
       }
       job.seg[job.G + 1 + g] = per;
@@ -531,6 +536,7 @@ __device__ void control_block(const Job &job) {
   if (threadIdx.x == 0) {
     job.seg[job.G] = carry;
     ctl->total = carry;
+    ctl->cursor.v = 0;
     ctl->sweep_id = sweep_id;
     ctl->iterations++;
     ctl->done = alldone;
@@ -559,6 +565,7 @@ struct Stage {
   uint32_t acc32;           // centers drawn (SELECT)
   uint32_t flush;           // a list passed the flush threshold
   uint32_t fmin;            // RELAX: smallest distance pushed on the next frontier
+  uint32_t chunk;           // next chunk of this workgroup
 };
 
 struct Out {
@@ -1243,13 +1250,20 @@ __device__ void sweep(const Job &job, uint32_t block, uint32_t nblocks, Stage &S
   if (threadIdx.x == 0) S.flush = 0;
   __syncthreads();
   uint32_t scanned = 0;
-  for (uint32_t v = block; v < total; v += nblocks) {
+  // chunk b first; chunks past the first nblocks go to whichever workgroup
+  // asks next, so that costly chunks (hub rows) do not hold up a sweep
+  for (uint32_t v = block; v < total;) {
     const int g = graph_of(job, v);
     const uint32_t per = job.seg[job.G + 1 + g];
     const uint32_t n_items = job.seg[2 * job.G + 1 + g];
     const uint32_t lo = (v - job.seg[g]) * per;
     const uint32_t hi = lo + per < n_items ? lo + per : n_items;
     scanned += process_run(job, g, lo, hi, it, S);
+    if (total <= nblocks) break;
+    if (threadIdx.x == 0) S.chunk = nblocks + atomicAdd(&job.ctl->cursor.v, 1u);
+    __syncthreads();
+    v = S.chunk;
+    __syncthreads();
   }
   for (int o = 32; o >= 1; o >>= 1) scanned += __shfl_xor(scanned, o);
   if (cld_lane() == 0 && scanned) atomicAdd(&job.ctl->arcs.v, (unsigned long long)scanned);
@@ -1432,6 +1446,11 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
   // synchronous steps (their sweeps take every active node)
   const int32_t rs = tuning ? tuning->row_bucket_shift : 0;
   d.row_shift = (rs < 0 || d.variant == CLDIAM_VARIANT_STEPS) ? -1 : (rs == 0 ? CLDIAM_ROW_SHIFT_DEFAULT : (rs > 31 ? 31 : rs));
+  // large dense graphs: the cost of a chunk varies with the hub rows it
+  // holds, so cut their frontiers finer and hand the chunks out on demand
+  const int32_t cf = tuning ? tuning->chunk_factor : 0;
+  d.chunk_factor = cf > 0 ? (cf > 64 ? 64 : cf)
+                          : ((x.m > (int64_t)kDenseDegree * x.n && x.n > kDenseLarge) ? kDenseChunks : 1);
   if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
   else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
   else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;

@@ -4,7 +4,7 @@ The knobs it chooses never change results: the driver (host-driven launches
 or one persistent cooperative kernel), the number of workgroup-local
 relaxation rounds per sweep, the number of workgroups per sweep and the
 distance-bucket widths of the relaxation sweeps (all nodes, and nodes with
-long rows).  Each
+long rows) and the number of growth chunks per workgroup.  Each
 candidate is timed on the job itself; the outputs of every candidate are
 checked to be identical to the first one's (a schedule that changed a result
 would be a bug).  The choice is cached per workload class (graph count and
@@ -23,6 +23,7 @@ CANDIDATES = (
     [dict(driver=DRIVER_HOST, local_rounds=r, grid_blocks=0) for r in (0, 2, 4, 8)]
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, bucket_width=w) for w in (4.0, 16.0, -1.0)]
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, row_bucket_shift=r) for r in (5, 11, -1)]
+    + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, chunk_factor=c) for c in (2, 4)]
     + [dict(driver=DRIVER_HOST, local_rounds=4, grid_blocks=128)]
     + [dict(driver=DRIVER_PERSISTENT, local_rounds=r, grid_blocks=128) for r in (0, 4)]
 )

@@ -56,6 +56,21 @@ def test_bucket_knobs_on_long_rows(bucket_width, row_shift, variant):
     assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
 
 
+@pytest.mark.parametrize("chunk_factor,grid_blocks,driver", [(1, 0, 1), (2, 7, 1), (7, 64, 1), (64, 300, 1),
+                                                             (5, 33, 2)])
+def test_chunk_factor_on_long_rows(chunk_factor, grid_blocks, driver):
+    """Growth chunks handed out on demand (any number per workgroup, either
+    driver) leave the R-MAT outputs equal to the oracle's."""
+    g = graphgen.rmat(14, seed=5)
+    _say(f"[systems] chunks factor={chunk_factor} blocks={grid_blocks} driver={driver}")
+    ref = oracle.decompose(g, 2, 6)
+    dg = cd.cldiam_load_csr(g)
+    c, D, st = cd.cldiam_decompose(dg, 2, 6, driver=driver, grid_blocks=grid_blocks, chunk_factor=chunk_factor)
+    assert np.array_equal(c.cpu().numpy(), ref.cluster)
+    assert np.array_equal(cd.u64(D), ref.D)
+    assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
+
+
 def test_batch_of_geometric_graphs_matches_oracle():
     sizes = [1000, 1500, 2500, 4000, 7000, 12000, 20000, 30000] * 3
     graphs = [graphgen.rgg(n, i, 5) for i, n in enumerate(sizes)]
