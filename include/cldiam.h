@@ -61,7 +61,7 @@ typedef struct {
   int32_t n;
   int32_t pad;
   int64_t m;
-  const int32_t *d_row_ptr; /* n+1 offsets, d_row_ptr[0] = 0, d_row_ptr[n] = m */
+  const int64_t *d_row_ptr; /* n+1 offsets, d_row_ptr[0] = 0, d_row_ptr[n] = m (m < 2^40) */
   const int32_t *d_col;     /* m column ids in [0, n) */
   const uint32_t *d_w;      /* m weights >= 1 */
 } cldiam_csr;
@@ -205,7 +205,7 @@ typedef struct {
   int32_t n;
   int32_t pad;
   int64_t m;
-  const int32_t *d_row_ptr; /* n+1 */
+  const int64_t *d_row_ptr; /* n+1 arc offsets, as passed to cldiam_load_csr */
   const uint64_t *d_arcs;   /* m packed arcs from cldiam_load_csr */
   uint64_t weight_sum;      /* sum of arc weights (cldiam_load_csr) */
   cldiam_params params;
@@ -267,7 +267,7 @@ int cldiam_server_poll(cldiam_server *server, uint64_t *h_tags, cldiam_stats *h_
  * and on the host *h_k = k and *h_qm = number of quotient arcs (2 x edges).
  * Arrays sized n+1 (row_ptr), n (center) and m (col, w) always suffice. */
 size_t cldiam_quotient_workspace_size(int32_t n, int64_t m);
-int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                           const int32_t *d_cluster, const uint64_t *d_D, int32_t *d_qcenter, int64_t *d_qrow_ptr,
                           int32_t *d_qcol, uint64_t *d_qw, int32_t *h_k, int64_t *h_qm, void *ws, size_t ws_bytes,
                           void *stream);
@@ -290,7 +290,7 @@ int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, c
  * bucket_delta = 0 picks the default width (the mean arc weight).  A finite
  * distance >= 0xFFFFFFFF returns CLDIAM_EOVERFLOW. */
 size_t cldiam_sssp_workspace_size(int32_t n, int64_t m);
-int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                                int32_t source, uint32_t bucket_delta, uint32_t *d_dist, uint64_t *h_max_dist,
                                void *ws, size_t ws_bytes, void *stream);
 

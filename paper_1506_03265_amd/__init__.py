@@ -158,7 +158,7 @@ class DeviceGraph:
     """Graph resident in device memory: CSR plus weight-sorted packed arcs."""
     n: int
     m: int
-    row_ptr: object      # torch int32 [n+1]
+    row_ptr: object      # torch int64 [n+1]
     col: object          # torch int32 [m]
     w: object            # torch int32 [m] (bit pattern of uint32)
     arcs: object         # torch int64 [m] (bit pattern of (w << 32) | col)
@@ -169,7 +169,7 @@ class DeviceGraph:
 def to_device(g, device="cuda"):
     """Copies a host CSR (graphgen.Graph) to device tensors (no validation)."""
     torch = _torch()
-    rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).to(device)
+    rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int64)).to(device)
     col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(device)
     w = torch.from_numpy(np.ascontiguousarray(g.w, dtype=np.uint32).view(np.int32)).to(device)
     return rp, col, w
@@ -193,9 +193,12 @@ def cldiam_load_csr(g, device="cuda", stream=None) -> DeviceGraph:
 
 
 def cldiam_load_csr_device(n, m, rp, col, w, stream=None) -> DeviceGraph:
-    """cldiam_load_csr on tensors already on the device."""
+    """cldiam_load_csr on tensors already on the device (row offsets int64,
+    columns int32, weights int32 holding uint32 bit patterns)."""
     torch = _torch()
     lib = load_library()
+    if rp.dtype != torch.int64 or col.dtype != torch.int32 or w.dtype != torch.int32:
+        raise TypeError("cldiam_load_csr_device: row offsets int64, columns and weights int32")
     arcs = torch.empty(max(m, 1), dtype=torch.int64, device=rp.device)
     csr = _Csr(n, 0, m, rp.data_ptr(), _ptr(col).value, _ptr(w).value)
     wsb = lib.cldiam_load_csr_workspace_size(n, m)

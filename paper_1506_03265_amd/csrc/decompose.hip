@@ -85,7 +85,7 @@ enum Phase : uint32_t {
 };
 
 struct GDesc {
-  const int32_t *row_ptr;
+  const int64_t *row_ptr;   // n+1 arc offsets
   const uint64_t *arcs;
   int32_t *cluster;
   uint64_t *D;
@@ -556,8 +556,8 @@ struct Stage {
   uint32_t mid_cnt, big_cnt;
   unsigned long long blk_min;  // workgroup minimum for the NEXT scan of a big row
   unsigned long long row_key;  // key of the big row being scanned
-  int32_t row_lo;              // end of its light prefix
-  int32_t row_start;           // first arc of its scan
+  int32_t row_lo;              // end of its light prefix (index within the row)
+  int32_t row_start;           // first arc of its scan (index within the row)
   uint32_t blk_hit;
   uint32_t cnt[3];
   uint32_t base[3];
@@ -645,12 +645,13 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
                                                uint32_t level_id, int32_t u,
                                                Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
   const uint64_t ku = job.key[off + u];
-  int32_t a0 = 0, a1 = 0;
+  int64_t a0 = 0;
+  int32_t deg = 0;   // a row has fewer than 2^31 arcs: indices within it are 32-bit
   bool later = (uint32_t)(ku >> 32) >= theta;
   if (!later) {
     a0 = d.row_ptr[u];
-    a1 = d.row_ptr[u + 1];
-    later = a1 - a0 > kMidDeg && (uint32_t)(ku >> 32) >= theta_row;
+    deg = (int32_t)(d.row_ptr[u + 1] - a0);
+    later = deg > kMidDeg && (uint32_t)(ku >> 32) >= theta_row;
   }
   if (later) {
     // beyond the current distance bucket: stays on the frontier for a later
@@ -661,18 +662,19 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
     }
     return 0;
   }
-  if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
+  if (deg > kMidDeg && defer_row(S, u, deg)) return 0;
+  const uint64_t *row = d.arcs + a0;
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
   uint32_t scanned = 0;
-  for (int32_t base = a0; base < a1 && !blocked; base += kArcBatch) {
+  for (int32_t base = 0; base < deg && !blocked; base += kArcBatch) {
     uint64_t arc[kArcBatch], cur[kArcBatch];
     bool ok[kArcBatch];
 #pragma unroll
-    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < a1 ? d.arcs[base + j] : ~0ull;
+    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < deg ? row[base + j] : ~0ull;
 #pragma unroll
     for (int j = 0; j < kArcBatch; ++j) {
-      const bool in = base + j < a1;
+      const bool in = base + j < deg;
       ok[j] = in && (uint32_t)(arc[j] >> 32) <= lim;
       if (in && !ok[j]) blocked = true;
       scanned += ok[j];
@@ -714,21 +716,22 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
 __device__ __forceinline__ uint32_t relax_sync(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
                                                uint32_t it, uint32_t level_id, int32_t u, Stage &S,
                                                const Out *out) {
-  const int32_t a0 = d.row_ptr[u];
-  const int32_t a1 = d.row_ptr[u + 1];
-  if (a1 - a0 > kMidDeg && defer_row(S, u, a1 - a0)) return 0;
+  const int64_t a0 = d.row_ptr[u];
+  const int32_t deg = (int32_t)(d.row_ptr[u + 1] - a0);
+  if (deg > kMidDeg && defer_row(S, u, deg)) return 0;
+  const uint64_t *row = d.arcs + a0;
   const uint64_t ku = job.key[off + u];
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
   uint32_t scanned = 0;
-  for (int32_t base = a0; base < a1 && !blocked; base += kArcBatch) {
+  for (int32_t base = 0; base < deg && !blocked; base += kArcBatch) {
     uint64_t arc[kArcBatch], cur[kArcBatch], old[kArcBatch];
     bool ok[kArcBatch], front[kArcBatch];
 #pragma unroll
-    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < a1 ? d.arcs[base + j] : ~0ull;
+    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < deg ? row[base + j] : ~0ull;
 #pragma unroll
     for (int j = 0; j < kArcBatch; ++j) {
-      const bool in = base + j < a1;
+      const bool in = base + j < deg;
       ok[j] = in && (uint32_t)(arc[j] >> 32) <= lim;
       if (in && !ok[j]) blocked = true;
       scanned += ok[j];
@@ -803,9 +806,11 @@ __device__ __forceinline__ uint64_t next_small(const Job &job, const GDesc &d, i
   const uint64_t ku = job.key[off + u];
   const uint32_t du = (uint32_t)(ku >> 32);
   const uint32_t lim = delta - du;
-  const int32_t a1 = d.row_ptr[u + 1];
-  for (int32_t a = d.row_ptr[u]; a < a1; ++a) {
-    const uint64_t arc = d.arcs[a];
+  const int64_t a0 = d.row_ptr[u];
+  const uint64_t *row = d.arcs + a0;
+  const int32_t deg = (int32_t)(d.row_ptr[u + 1] - a0);
+  for (int32_t a = 0; a < deg; ++a) {
+    const uint64_t arc = row[a];
     const uint32_t w = (uint32_t)(arc >> 32);
     if (w <= lim) continue;
     if (job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64) return (uint64_t)du + w;
@@ -850,10 +855,11 @@ __device__ __forceinline__ int32_t wave_first_above(const uint64_t *arcs, int32_
   return m ? lo + (__ffsll((long long)m) - 1) : hi;
 }
 
-__device__ __forceinline__ int32_t resume_at_wave(const Job &job, const GDesc &d, int64_t off, int32_t u,
-                                                  uint64_t ku, int32_t a0, int32_t a1) {
-  if (job.keyn[off + u] != ku) return a0;
-  return wave_first_above(d.arcs, a0, a1, job.slim[off + u]);
+// Resume index within the row [0, end) of u (arcs at row).
+__device__ __forceinline__ int32_t resume_at_wave(const Job &job, int64_t off, int32_t u, uint64_t ku,
+                                                  const uint64_t *row, int32_t end) {
+  if (job.keyn[off + u] != ku) return 0;
+  return wave_first_above(row, 0, end, job.slim[off + u]);
 }
 
 __device__ __forceinline__ void note_scan(const Job &job, int64_t off, int32_t u, uint64_t ku, uint32_t lim) {
@@ -876,14 +882,16 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   uint32_t scanned = 0;
   for (uint32_t r = wave; r < nm; r += nwaves) {
     const int32_t u = S.mid[r];
-    const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
+    const int64_t a0 = d.row_ptr[u];
+    const int32_t a1 = (int32_t)(d.row_ptr[u + 1] - a0);   // row-relative from here on
+    const uint64_t *row = d.arcs + a0;
     const uint64_t ku = job.key[off + u];
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
     if (mode != 1) {
-      const int32_t start = resume ? resume_at_wave(job, d, off, u, ku, a0, a1) : a0;
+      const int32_t start = resume ? resume_at_wave(job, off, u, ku, row, a1) : 0;
       for (int32_t base = start; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
-        const uint64_t arc = a < a1 ? d.arcs[a] : ~0ull;
+        const uint64_t arc = a < a1 ? row[a] : ~0ull;
         const bool light = a < a1 && (uint32_t)(arc >> 32) <= lim;
         if (!__any(light)) break;
         if (light) {
@@ -892,13 +900,13 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
           else relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq);
         }
       }
-      if (lane == 0 && (uint32_t)(d.arcs[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
+      if (lane == 0 && (uint32_t)(row[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
       if (resume && lane == 0) note_scan(job, off, u, ku, lim);
     } else {
       // the heavy arcs start after the light prefix
-      for (int32_t base = wave_first_above(d.arcs, a0, a1, lim); base < a1; base += 64) {
+      for (int32_t base = wave_first_above(row, 0, a1, lim); base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
-        const uint64_t arc = a < a1 ? d.arcs[a] : 0ull;
+        const uint64_t arc = a < a1 ? row[a] : 0ull;
         const uint32_t w = (uint32_t)(arc >> 32);
         const bool hit = a < a1 && w > lim && job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64;
         const unsigned long long m = __ballot(hit);
@@ -914,14 +922,16 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   }
   for (uint32_t h = 0; h < nb; ++h) {
     const int32_t u = S.big[h];
-    const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
+    const int64_t a0 = d.row_ptr[u];
+    const int32_t a1 = (int32_t)(d.row_ptr[u + 1] - a0);   // row-relative from here on
+    const uint64_t *row = d.arcs + a0;
     // wave 0 reads u's key once for the whole workgroup (so every thread scans
     // with the same key and the scan record describes all of them) and finds
     // the end of the light prefix and the resume point
     if (threadIdx.x < 64) {
       const uint64_t k = job.key[off + u];
-      const int32_t light_end = wave_first_above(d.arcs, a0, a1, delta - (uint32_t)(k >> 32));
-      const int32_t from = (mode != 1 && resume) ? resume_at_wave(job, d, off, u, k, a0, light_end) : a0;
+      const int32_t light_end = wave_first_above(row, 0, a1, delta - (uint32_t)(k >> 32));
+      const int32_t from = (mode != 1 && resume) ? resume_at_wave(job, off, u, k, row, light_end) : 0;
       if (threadIdx.x == 0) {
         S.row_key = k;
         S.row_lo = light_end;
@@ -936,8 +946,8 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       const int32_t start = S.row_start;
       for (int32_t a = start + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
         ++scanned;
-        if (mode == 2) relax_one_sync(job, off, ku, d.arcs[a], it, S, out);
-        else relax_one(job, off, ku, d.arcs[a], it, S, out, lq_cnt, lq);
+        if (mode == 2) relax_one_sync(job, off, ku, row[a], it, S, out);
+        else relax_one(job, off, ku, row[a], it, S, out, lq_cnt, lq);
       }
       if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
       // keep LDS staging within bounds between rows
@@ -953,7 +963,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
         __syncthreads();
         const int32_t a = base + (int32_t)threadIdx.x;
         if (a < a1) {
-          const uint64_t arc = d.arcs[a];
+          const uint64_t arc = row[a];
           if (job.key[off + (int32_t)(uint32_t)arc] == CLD_INF64) {
             const uint64_t c = (uint64_t)(uint32_t)(ku >> 32) + (uint32_t)(arc >> 32);
             atomicMin(&S.blk_min, (unsigned long long)c);
@@ -982,15 +992,17 @@ __device__ uint32_t c2_boundary(const Job &job, const GDesc &d, int64_t off, uin
                                 Stage &S, const Out *out) {
   const uint32_t dl = (uint32_t)job.keyn[off + u];
   const uint64_t label = job.key[off + u] & 0xffffffffull;
-  const int32_t a0 = d.row_ptr[u], a1 = d.row_ptr[u + 1];
-  int32_t lo = a0, hi = a1;
+  const int64_t a0 = d.row_ptr[u];
+  const int32_t a1 = (int32_t)(d.row_ptr[u + 1] - a0);
+  const uint64_t *row = d.arcs + a0;
+  int32_t lo = 0, hi = a1;
   while (lo < hi) {   // first arc with w > delta2 - dl
     const int32_t mid = lo + ((hi - lo) >> 1);
-    if ((uint32_t)(d.arcs[mid] >> 32) <= delta2 - dl) lo = mid + 1; else hi = mid;
+    if ((uint32_t)(row[mid] >> 32) <= delta2 - dl) lo = mid + 1; else hi = mid;
   }
   uint32_t scanned = 0;
   for (int32_t a = lo; a < a1; ++a) {
-    const uint64_t arc = d.arcs[a];
+    const uint64_t arc = row[a];
     const uint32_t w = (uint32_t)(arc >> 32);
     if (w > delta2) break;
     ++scanned;
@@ -1132,7 +1144,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
         }
         case PH_NEXT: {
           const int32_t u = job.pool[blk][off + idx];
-          const int32_t deg = d.row_ptr[u + 1] - d.row_ptr[u];
+          const int32_t deg = (int32_t)(d.row_ptr[u + 1] - d.row_ptr[u]);
           if (deg > kMidDeg && defer_row(S, u, deg)) break;
           const uint64_t best = next_small(job, d, off, delta, u);
           if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
@@ -1416,7 +1428,7 @@ int grid_blocks(int driver, int requested, int *blocks) {
 // Descriptor of one graph (node offset set by the caller); returns a status.
 int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *out) {
   float bucket_width = tuning ? tuning->bucket_width : 0.f;
-  if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 31) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
+  if (x.n < 1 || x.m < 0 || x.m >= ((int64_t)1 << 40) || !x.d_row_ptr || (x.m && !x.d_arcs) || !x.d_cluster ||
       !x.d_D || x.params.tau < 1) {
     cld::set_error("decompose: invalid graph %d (n=%d m=%lld tau=%u)", g, x.n, (long long)x.m, x.params.tau);
     return CLDIAM_EINVAL;

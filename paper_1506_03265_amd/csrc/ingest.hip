@@ -36,7 +36,7 @@ struct IngestCtl {
   unsigned long long wsum;
 };
 
-__global__ void k_check_rows(const int32_t *rp, int32_t n, int64_t m, IngestCtl *ctl) {
+__global__ void k_check_rows(const int64_t *rp, int32_t n, int64_t m, IngestCtl *ctl) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     bool ok = rp[i] <= rp[i + 1] && rp[i] >= 0 && rp[i + 1] <= m;
     if (i == 0) ok = ok && rp[0] == 0;
@@ -46,7 +46,7 @@ __global__ void k_check_rows(const int32_t *rp, int32_t n, int64_t m, IngestCtl 
 }
 
 // One wave per row: validates every arc of the row and packs it.
-__global__ void __launch_bounds__(kT) k_validate_pack(const int32_t *rp, const int32_t *col, const uint32_t *w,
+__global__ void __launch_bounds__(kT) k_validate_pack(const int64_t *rp, const int32_t *col, const uint32_t *w,
                                                       int32_t n, uint64_t *arcs, IngestCtl *ctl) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(kT) k_validate_pack(const int32_t *rp, const i
   uint32_t bad = 0;
   unsigned long long wsum = 0;
   for (int64_t u = wave; u < n; u += nwaves) {
-    const int32_t a0 = rp[u], a1 = rp[u + 1];
-    for (int32_t a = a0 + lane; a < a1; a += 64) {
+    const int64_t a0 = rp[u], a1 = rp[u + 1];
+    for (int64_t a = a0 + lane; a < a1; a += 64) {
       const int32_t v = col[a];
       const uint32_t wt = w[a];
       wsum += wt;
@@ -64,10 +64,10 @@ __global__ void __launch_bounds__(kT) k_validate_pack(const int32_t *rp, const i
       if (a > a0 && col[a - 1] >= v) bad |= BAD_ORDER;
       if (wt == 0) bad |= BAD_WEIGHT;
       // reverse arc v -> u by binary search in row v (sorted by column)
-      int32_t lo = rp[v], hi = rp[v + 1] - 1;
+      int64_t lo = rp[v], hi = rp[v + 1] - 1;
       bool found = false;
       while (lo <= hi) {
-        const int32_t mid = lo + ((hi - lo) >> 1);
+        const int64_t mid = lo + ((hi - lo) >> 1);
         const int32_t c = col[mid];
         if (c == (int32_t)u) { found = (w[mid] == wt); break; }
         if (c < (int32_t)u) lo = mid + 1; else hi = mid - 1;
@@ -87,14 +87,14 @@ __global__ void __launch_bounds__(kT) k_validate_pack(const int32_t *rp, const i
 }
 
 // Small rows sorted in place by one thread; larger rows queued by size class.
-__global__ void k_small_sort(const int32_t *rp, int32_t n, uint64_t *arcs, int32_t *mid, int32_t *big,
+__global__ void k_small_sort(const int64_t *rp, int32_t n, uint64_t *arcs, int32_t *mid, int32_t *big,
                              IngestCtl *ctl) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a0 = rp[u], a1 = rp[u + 1], deg = a1 - a0;
+    const int64_t a0 = rp[u], a1 = rp[u + 1], deg = a1 - a0;
     if (deg <= kSmallRow) {
-      for (int32_t i = a0 + 1; i < a1; ++i) {
+      for (int64_t i = a0 + 1; i < a1; ++i) {
         const uint64_t x = arcs[i];
-        int32_t j = i - 1;
+        int64_t j = i - 1;
         while (j >= a0 && arcs[j] > x) { arcs[j + 1] = arcs[j]; --j; }
         arcs[j + 1] = x;
       }
@@ -107,12 +107,13 @@ __global__ void k_small_sort(const int32_t *rp, int32_t n, uint64_t *arcs, int32
 }
 
 // One block per mid-size row: bitonic sort of the row in LDS.
-__global__ void __launch_bounds__(1024) k_mid_sort(const int32_t *rp, const int32_t *rows, const IngestCtl *ctl,
+__global__ void __launch_bounds__(1024) k_mid_sort(const int64_t *rp, const int32_t *rows, const IngestCtl *ctl,
                                                    uint64_t *arcs) {
   __shared__ uint64_t s[kLdsRow];
   for (uint32_t r = blockIdx.x; r < ctl->nmid; r += gridDim.x) {
     const int32_t u = rows[r];
-    const int32_t a0 = rp[u], deg = rp[u + 1] - a0;
+    const int64_t a0 = rp[u];
+    const int32_t deg = (int32_t)(rp[u + 1] - a0);
     int size = 1;
     while (size < deg) size <<= 1;
     for (int i = threadIdx.x; i < size; i += blockDim.x) s[i] = i < deg ? arcs[a0 + i] : ~(uint64_t)0;
@@ -152,7 +153,7 @@ extern "C" size_t cldiam_load_csr_workspace_size(int32_t n, int64_t m) {
 extern "C" int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *h_weight_sum, void *ws,
                                size_t ws_bytes, void *stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  if (!g || g->n < 1 || g->m < 0 || g->m >= ((int64_t)1 << 31) || !g->d_row_ptr || (g->m && (!g->d_col || !g->d_w || !d_arcs))) {
+  if (!g || g->n < 1 || g->m < 0 || g->m >= ((int64_t)1 << 40) || !g->d_row_ptr || (g->m && (!g->d_col || !g->d_w || !d_arcs))) {
     cld::set_error("load_csr: invalid arguments");
     return CLDIAM_EINVAL;
   }
@@ -194,9 +195,10 @@ extern "C" int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *
       CLD_LAUNCH_CHECK("k_mid_sort");
     }
     if (h.nbig) {
-      std::vector<int32_t> rows(h.nbig), rp(n + 1);
+      std::vector<int32_t> rows(h.nbig);
+      std::vector<int64_t> rp(n + 1);
       CLD_HIP(hipMemcpyAsync(rows.data(), big, 4 * (size_t)h.nbig, hipMemcpyDeviceToHost, stream));
-      CLD_HIP(hipMemcpyAsync(rp.data(), g->d_row_ptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, stream));
+      CLD_HIP(hipMemcpyAsync(rp.data(), g->d_row_ptr, 8 * ((size_t)n + 1), hipMemcpyDeviceToHost, stream));
       CLD_HIP(hipStreamSynchronize(stream));
       for (int32_t u : rows) {
         const int64_t a0 = rp[u], deg = rp[u + 1] - rp[u];

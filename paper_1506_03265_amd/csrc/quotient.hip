@@ -27,10 +27,11 @@ namespace {
 constexpr int kT = 256;
 
 struct QCtl {
+  unsigned long long pairs;   // emitted arcs
   uint32_t k;
-  uint32_t pairs;   // emitted arcs
   uint32_t uniq;    // quotient arcs
   uint32_t wide;    // some D does not fit the packed node word
+  uint32_t pad;
 };
 
 __global__ void k_center_flags(const int32_t *cluster, int32_t n, uint32_t *flag) {
@@ -84,7 +85,8 @@ struct EmitState {
   unsigned long long hval[kHashCap];
   int32_t mid[kEmitDefer];
   int32_t big[kEmitDefer];
-  uint32_t nmid, nbig, used, base, cursor;
+  unsigned long long base;
+  uint32_t nmid, nbig, used, cursor;
 };
 
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
@@ -104,7 +106,7 @@ __device__ __forceinline__ void emit_pair(EmitState &E, uint64_t key, uint64_t v
     }
     h = (h + 1) & (kHashCap - 1);
   }
-  const uint32_t at = atomicAdd(&ctl->pairs, 1u);
+  const unsigned long long at = atomicAdd(&ctl->pairs, 1ull);
   keys[at] = key;
   vals[at] = val;
 }
@@ -112,13 +114,13 @@ __device__ __forceinline__ void emit_pair(EmitState &E, uint64_t key, uint64_t v
 __device__ void hash_flush(EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    E.base = E.used ? atomicAdd(&ctl->pairs, E.used) : 0;
+    E.base = E.used ? atomicAdd(&ctl->pairs, (unsigned long long)E.used) : 0ull;
     E.cursor = 0;
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < kHashCap; i += blockDim.x) {
     if (E.hkey[i] != ~0ull) {
-      const uint32_t at = E.base + atomicAdd(&E.cursor, 1u);
+      const unsigned long long at = E.base + atomicAdd(&E.cursor, 1u);
       keys[at] = E.hkey[i];
       vals[at] = E.hval[i];
       E.hkey[i] = ~0ull;
@@ -172,7 +174,7 @@ __device__ __forceinline__ void emit_arc(uint64_t arc, uint32_t cu, uint64_t du,
 }
 
 template <bool kPacked>
-__global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const uint64_t *arcs, int32_t n, NodeIn in,
+__global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const uint64_t *arcs, int32_t n, NodeIn in,
                                                        int kb, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
   __shared__ EmitState E;
   for (uint32_t i = threadIdx.x; i < kHashCap; i += blockDim.x) { E.hkey[i] = ~0ull; E.hval[i] = ~0ull; }
@@ -185,8 +187,8 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const 
   for (int64_t r = lo; r < hi; r += blockDim.x) {
     const int64_t u = r + threadIdx.x;
     if (u < hi) {
-      const int32_t a0 = rp[u], a1 = rp[u + 1];
-      const int32_t deg = a1 - a0;
+      const int64_t a0 = rp[u];
+      const int32_t deg = (int32_t)(rp[u + 1] - a0);
       bool done = false;
       if (deg > kEmitThreadDeg) {
         uint32_t *cnt = deg > kEmitBlockDeg ? &E.nbig : &E.nmid;
@@ -198,29 +200,34 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int32_t *rp, const 
         uint32_t cu;
         uint64_t du, ka;
         node_of<kPacked>(in, (int32_t)u, kb, &cu, &du, &ka);
-        for (int32_t a = a0; a < a1; ++a) emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
+        const uint64_t *row = arcs + a0;
+        for (int32_t a = 0; a < deg; ++a) emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
       }
     }
     __syncthreads();
     const uint32_t nm = E.nmid < kEmitDefer ? E.nmid : kEmitDefer;
     for (uint32_t i = wave; i < nm; i += nwaves) {
       const int32_t u = E.mid[i];
-      const int32_t a0 = rp[u], a1 = rp[u + 1];
+      const int64_t a0 = rp[u];
+      const int32_t deg = (int32_t)(rp[u + 1] - a0);
+      const uint64_t *row = arcs + a0;
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
-      for (int32_t a = a0 + (int32_t)lane; a < a1; a += 64)
-        emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
+      for (int32_t a = (int32_t)lane; a < deg; a += 64)
+        emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
     }
     const uint32_t nbg = E.nbig < kEmitDefer ? E.nbig : kEmitDefer;
     for (uint32_t i = 0; i < nbg; ++i) {
       const int32_t u = E.big[i];
-      const int32_t a0 = rp[u], a1 = rp[u + 1];
+      const int64_t a0 = rp[u];
+      const int32_t deg = (int32_t)(rp[u + 1] - a0);
+      const uint64_t *row = arcs + a0;
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
-      for (int32_t a = a0 + (int32_t)threadIdx.x; a < a1; a += (int32_t)blockDim.x)
-        emit_arc<kPacked>(arcs[a], cu, du, ka, in, E, keys, vals, ctl);
+      for (int32_t a = (int32_t)threadIdx.x; a < deg; a += (int32_t)blockDim.x)
+        emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
       __syncthreads();
       if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
     }
@@ -323,12 +330,12 @@ extern "C" size_t cldiam_quotient_workspace_size(int32_t n, int64_t m) {
   return s.s.used + (extra > sc ? extra : sc);
 }
 
-extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                                      const int32_t *d_cluster, const uint64_t *d_D, int32_t *d_qcenter,
                                      int64_t *d_qrow_ptr, int32_t *d_qcol, uint64_t *d_qw, int32_t *h_k,
                                      int64_t *h_qm, void *ws, size_t ws_bytes, void *stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  if (n < 1 || m < 0 || m >= ((int64_t)1 << 31) || !d_row_ptr || (m && !d_arcs) || !d_cluster || !d_D ||
+  if (n < 1 || m < 0 || m >= ((int64_t)1 << 40) || !d_row_ptr || (m && !d_arcs) || !d_cluster || !d_D ||
       !d_qcenter || !d_qrow_ptr || !h_k || !h_qm) {
     cld::set_error("build_quotient: invalid arguments");
     return CLDIAM_EINVAL;
@@ -373,7 +380,12 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int32_t *d_row_
   }
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
-  const int64_t P = h.pairs;
+  const int64_t P = (int64_t)h.pairs;
+  if (P >= (int64_t)0xffffffff) {
+    cld::set_error("build_quotient: %lld distinct cluster pairs exceed the 2^32 - 1 the run numbering holds",
+                   (long long)P);
+    return CLDIAM_EOVERFLOW;
+  }
   bool in_tmp = false;
   rc = cld::radix_sort_u64(keys, vals, P, 0, 2 * kb, ktmp, vtmp, &in_tmp, rest, rest_bytes, stream);
   if (rc) return rc;

@@ -52,7 +52,7 @@ struct SCtl {
 };
 
 struct SJob {
-  const int32_t *rp;
+  const int64_t *rp;
   const uint64_t *arcs;
   int32_t n;
   uint32_t delta;
@@ -149,7 +149,7 @@ __device__ void s_item(const SJob &j, uint32_t i, uint32_t phase, uint32_t it) {
       bool addr = j.rstamp[u] != bucket + 1 && atomicExch(&j.rstamp[u], bucket + 1) != bucket + 1;
       uint32_t s = cld_wave_reserve(addr, &c->cntR.v);
       if (addr) j.R[s] = u;
-      for (int32_t a = j.rp[u]; a < j.rp[u + 1]; ++a) {
+      for (int64_t a = j.rp[u]; a < j.rp[u + 1]; ++a) {
         const uint64_t arc = j.arcs[a];
         const uint64_t w = arc >> 32;
         if (w > delta) break;
@@ -160,7 +160,7 @@ __device__ void s_item(const SJob &j, uint32_t i, uint32_t phase, uint32_t it) {
     case S_HEAVY: {
       const int32_t u = j.R[i];
       const uint64_t du = j.dist[u];
-      for (int32_t a = j.rp[u + 1] - 1; a >= j.rp[u]; --a) {
+      for (int64_t a = j.rp[u + 1] - 1; a >= j.rp[u]; --a) {
         const uint64_t arc = j.arcs[a];
         const uint64_t w = arc >> 32;
         if (w <= delta) break;
@@ -256,7 +256,7 @@ extern "C" size_t cldiam_sssp_workspace_size(int32_t n, int64_t m) {
   return s.used;
 }
 
-extern "C" int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int32_t *d_row_ptr, const uint64_t *d_arcs,
+extern "C" int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                                           int32_t source, uint32_t bucket_delta, uint32_t *d_dist,
                                           uint64_t *h_max_dist, void *ws, size_t ws_bytes, void *stream_) {
   hipStream_t stream = (hipStream_t)stream_;
