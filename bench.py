@@ -33,6 +33,9 @@ Other workloads (each prints its own JSON line):
   --workload delta0   the initial-Delta experiment on a bimodal-weight mesh
   --workload stepcap  the growing-step cap on skewed graphs
   --workload ceilings random-access ceilings of the GPU (PyTorch kernels)
+  --workload mesh29   the step on a 2^29-node mesh with 2.16G arcs (64-bit
+                      row offsets), checked by properties that hold at any
+                      size (the oracle cannot run it)
 
 Only one GPU is supported.
 """
@@ -503,6 +506,109 @@ def ceilings_bench(args):
     }
 
 
+def mesh29_bench(args):
+    """The whole step on a 16384 x 32768 mesh with 1% diagonals: 2^29 nodes
+    (R-MAT scale 29's node count) and 2,158M arcs, beyond 32-bit row offsets.
+    No oracle run fits this size; the run checks properties that hold at any
+    size: every node is labelled by a center that labels itself at D = 0, the
+    labels are the quotient's nodes, for two clusters the exact distances from
+    their centers (Delta-stepping SSSP) never exceed D, and Phi_approx is at
+    least every such eccentricity."""
+    import torch
+
+    import graphgen
+    import paper_1506_03265_amd as cd
+
+    tau, seed = 4, 1
+    rows, cols = (int(x) for x in args.mesh_shape.split("x"))
+    log(f"[bench] generating the {rows} x {cols} mesh with 1% diagonals")
+    t0 = time.perf_counter()
+    g = graphgen.mesh64(rows, cols, 10**4, 1, 0.01)
+    gen_s = time.perf_counter() - t0
+    n, m = g.n, g.m
+    log(f"[bench] generated n={n} m={m} arcs in {gen_s:.1f} s")
+    torch.cuda.init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dg = cd.cldiam_load_csr(g)
+    torch.cuda.synchronize()
+    ingest_ms = (time.perf_counter() - t0) * 1e3
+    del g
+    torch.cuda.empty_cache()
+    log(f"[bench] ingest {ingest_ms:.0f} ms (H2D + validation + packing)")
+    job = cd.DecomposeJob([dg], [(tau, seed, 0)], driver=args.driver)
+    qjob = cd.QuotientJob(dg)
+    ejob = cd.EstimateJob(1, 1, dg.row_ptr.device)
+
+    def step():
+        ta = time.perf_counter()
+        st = job.run()[0]
+        tb = time.perf_counter()
+        q = qjob.run(job.cluster[0], job.D[0])
+        tc = time.perf_counter()
+        est = ejob.run(q, st.radius)
+        td = time.perf_counter()
+        return st, q, est, (tb - ta, tc - tb, td - tc)
+
+    for i in range(args.warmup):
+        st, q, est, ph = step()
+        log(f"[bench] warmup {i}: decompose {ph[0] * 1e3:.1f} ms, quotient {ph[1] * 1e3:.1f} ms, "
+            f"{st.sweeps} sweeps, {st.num_clusters} clusters")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phases = []
+    for i in range(args.steps):
+        st, q, est, ph = step()
+        phases.append(ph)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log(f"[bench] {args.steps} steps: {ms:.1f} ms/step")
+
+    # properties that hold at any size
+    cl = job.cluster[0]
+    D = job.D[0]
+    assert int(cl.min()) >= 0 and int(cl.max()) < n, "a node without a valid label"
+    lab = cl.long()
+    assert bool((cl[lab] == cl).all()), "a label that is not a center"
+    centers = torch.nonzero(cl == torch.arange(n, device=cl.device, dtype=torch.int32)).flatten()
+    assert bool((D[centers] == 0).all()), "a center with D > 0"
+    assert centers.numel() == st.num_clusters == q.k, "centers, cluster count and quotient size differ"
+    assert bool((q.center.long() == centers).all()), "quotient nodes are not the centers in ascending order"
+    phi, approx = est
+    del qjob, q
+    torch.cuda.empty_cache()
+    checks = []
+    for v in (0, n - 1):
+        c = int(cl[v])
+        dist, ecc = cd.cldiam_sssp_delta_stepping(dg, c)
+        mine = cl == c
+        dd = dist.long() & 0xFFFFFFFF
+        assert bool((dd[mine] <= D[mine]).all()), f"D below the exact distance in cluster {c}"
+        assert ecc <= approx, f"Phi_approx {approx} below the eccentricity {ecc} of node {c}"
+        checks.append({"center": c, "nodes": int(mine.sum()), "ecc": ecc, "max_D": int(D[mine].max())})
+        del dist, dd, mine
+    log(f"[bench] checks passed: {checks}")
+    dec_ms = sum(p[0] for p in phases) / len(phases) * 1e3
+    quot_ms = sum(p[1] for p in phases) / len(phases) * 1e3
+    est_ms = sum(p[2] for p in phases) / len(phases) * 1e3
+    edges = m // 2
+    return {
+        "metric": "decomposition GTEPS on a mesh past 32-bit row offsets",
+        "value": round(edges / (ms / 1e3) / 1e9, 6), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{rows}x{cols} mesh, every grid edge, 1% diagonals, weights uniform in [1, 1e4], "
+                               f"graph seed 1, tau={tau}, seed={seed}, step = decompose + quotient + estimate",
+                   "n": n, "m_arcs": m, "edges": edges, "generate_s": round(gen_s, 1),
+                   "ingest_ms": round(ingest_ms, 1), "decompose_ms": round(dec_ms, 2),
+                   "quotient_ms": round(quot_ms, 2), "estimate_ms": round(est_ms, 3),
+                   "clusters": st.num_clusters, "stages": st.stages, "levels": st.levels, "radius": st.radius,
+                   "sweeps": st.sweeps, "arcs_relaxed": st.arcs_scanned, "phi_gc": phi, "phi_approx": approx,
+                   "property_checks": checks},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def sssp_bench(args):
     import torch
 
@@ -559,8 +665,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="road4096",
                     choices=["road4096", "rmat24", "rgg256", "serve", "sssp", "variants", "delta0", "stepcap",
-                             "ceilings"])
+                             "ceilings", "mesh29"])
     ap.add_argument("--side", type=int, default=2048, help="delta0: mesh side")
+    ap.add_argument("--mesh-shape", default="16384x32768", help="mesh29: rows x cols")
     ap.add_argument("--tau", type=int, default=4, help="delta0 / stepcap: tau")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--driver", type=int, default=0, help="0 auto, 1 host-driven, 2 persistent")
@@ -610,6 +717,8 @@ def main():
         out = stepcap_bench(args)
     elif args.workload == "ceilings":
         out = ceilings_bench(args)
+    elif args.workload == "mesh29":
+        out = mesh29_bench(args)
     else:
         out = serve_bench(args)
     print(json.dumps(out), flush=True)

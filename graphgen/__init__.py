@@ -66,6 +66,8 @@ def _load():
         lib.gg_rgg_size.restype = ctypes.c_int32
         lib.gg_from_edges.argtypes = [ctypes.c_int64, ctypes.c_int64, P(ctypes.c_uint32), P(ctypes.c_uint32),
                                       P(ctypes.c_uint32), P(_CSR)]
+        lib.gg_mesh64.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                  ctypes.c_uint32, P(_CSR)]
         lib.gg_free.argtypes = [P(_CSR)]
         lib.gg_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
         _lib = lib
@@ -76,7 +78,7 @@ def _load():
 class Graph:
     """Undirected weighted graph as a symmetric CSR (rows sorted by column)."""
     n: int
-    row_ptr: np.ndarray  # int32[n+1]
+    row_ptr: np.ndarray  # int32[n+1] (int64 from mesh64)
     col: np.ndarray      # int32[m]
     w: np.ndarray        # uint32[m]
     name: str = ""
@@ -121,6 +123,43 @@ def grid(rows: int, cols: int, wmax: int, seed: int, drop_p: float = 0.0, diag_p
     if rc != 0:
         raise RuntimeError("gg_grid failed")
     return _take(c, f"grid{rows}x{cols}")
+
+
+def mesh64(rows: int, cols: int, wmax: int, seed: int, diag_p: float = 0.0) -> Graph:
+    """Full rows x cols grid plus the diagonals of grid() (same draws and
+    weights; equal to grid(rows, cols, wmax, seed, 0, diag_p)), written
+    straight to a CSR with int64 row offsets: sizes past 2^31 arcs."""
+    c = _CSR()
+    rc = _load().gg_mesh64(rows, cols, wmax, seed, _thr(diag_p), ctypes.byref(c))
+    if rc != 0:
+        raise RuntimeError("gg_mesh64 failed")
+    n, m = int(c.n), int(c.m)
+    owner = _Owned(c)   # the arrays view the C buffers, which live as long as any of them
+
+    def view(ptr, ctype, count, dtype):
+        buf = (ctype * count).from_address(ctypes.addressof(ptr.contents))
+        buf._owner = owner
+        return np.frombuffer(buf, dtype=dtype)
+
+    return Graph(n, view(c.row_ptr64, ctypes.c_int64, n + 1, np.int64), view(c.col, ctypes.c_int32, m, np.int32),
+                 view(c.w, ctypes.c_uint32, m, np.uint32), f"mesh{rows}x{cols}")
+
+
+class _Owned:
+    """Frees a generator's C buffers when the last array viewing them goes."""
+
+    def __init__(self, c: "_CSR"):
+        self.c = c
+
+    def __del__(self):
+        _load().gg_free(ctypes.byref(self.c))
+
+
+def mesh29(seed: int = 1) -> Graph:
+    """16384 x 32768 mesh (2^29 nodes, the node count of R-MAT scale 29) with
+    1% diagonals, weights uniform in [1, 10^4]: 2,158M arcs, past the reach of
+    32-bit row offsets."""
+    return mesh64(16384, 32768, 10**4, seed, 0.01)
 
 
 def grid_small(seed: int = 1) -> Graph:

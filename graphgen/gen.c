@@ -241,6 +241,78 @@ fail:
   return -1;
 }
 
+/* rows x cols grid with every grid edge kept plus the diagonals of gg_grid
+ * (same draws, same weights: for sizes gg_grid takes and drop_thr = 0 the
+ * two produce the same CSR).  A full grid is connected, so the CSR is written
+ * directly, two passes over the nodes (degrees, then arcs) with no edge list
+ * and no component search; offsets are int64 (row_ptr64 only, row_ptr stays
+ * NULL), for graphs of more than 2^31 arcs. */
+int gg_mesh64(int32_t rows, int32_t cols, uint32_t wmax, uint64_t seed, uint32_t diag_thr, gg_csr *out) {
+  memset(out, 0, sizeof *out);
+  if (rows < 2 || cols < 2 || wmax < 1 || (int64_t)rows * cols > 0x7fffffff) return -1;
+  const int64_t n = (int64_t)rows * cols, cells = (int64_t)(rows - 1) * (cols - 1);
+  const int64_t H = (int64_t)rows * (cols - 1), V = (int64_t)(rows - 1) * cols;
+  /* diagonal of each cell: 0 none, 1 (r,c)-(r+1,c+1), 2 (r,c+1)-(r+1,c) */
+  uint8_t *dg = calloc((size_t)cells, 1);
+  int64_t *rp = malloc(((size_t)n + 1) * 8);
+  if (!dg || !rp) { free(dg); free(rp); return -1; }
+  if (diag_thr) {
+#pragma omp parallel for schedule(static)
+    for (int64_t cell = 0; cell < cells; ++cell) {
+      uint32_t cc[4] = {(uint32_t)cell, 0, TAG_DIAG, 0}, o[4];
+      philox(cc, seed, o);
+      if (o[0] < diag_thr) dg[cell] = (o[1] & 1u) ? 2 : 1;
+    }
+  }
+  /* neighbours of (r,c) in ascending id: up-left, up, up-right, left, right,
+   * down-left, down, down-right; k-th entry valid when nb_ok */
+#define CELL(r, c) ((int64_t)(r) * (cols - 1) + (c))
+  rp[0] = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t r = (int32_t)(v / cols), c = (int32_t)(v % cols);
+    int d = 0;
+    if (r > 0 && c > 0 && dg[CELL(r - 1, c - 1)] == 1) d++;
+    if (r > 0) d++;
+    if (r > 0 && c + 1 < cols && dg[CELL(r - 1, c)] == 2) d++;
+    if (c > 0) d++;
+    if (c + 1 < cols) d++;
+    if (r + 1 < rows && c > 0 && dg[CELL(r, c - 1)] == 2) d++;
+    if (r + 1 < rows) d++;
+    if (r + 1 < rows && c + 1 < cols && dg[CELL(r, c)] == 1) d++;
+    rp[v + 1] = d;
+  }
+  for (int64_t v = 0; v < n; ++v) rp[v + 1] += rp[v];
+  const int64_t m = rp[n];
+  int32_t *col = malloc((size_t)m * 4);
+  uint32_t *w = malloc((size_t)m * 4);
+  if (!col || !w) { free(dg); free(rp); free(col); free(w); return -1; }
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t r = (int32_t)(v / cols), c = (int32_t)(v % cols);
+    int64_t a = rp[v];
+#define ARC(nb, idx) do { col[a] = (int32_t)(nb); w[a] = weight_draw((uint64_t)(idx), seed, wmax); a++; } while (0)
+    if (r > 0 && c > 0 && dg[CELL(r - 1, c - 1)] == 1) ARC(v - cols - 1, H + V + CELL(r - 1, c - 1));
+    if (r > 0) ARC(v - cols, H + (int64_t)(r - 1) * cols + c);
+    if (r > 0 && c + 1 < cols && dg[CELL(r - 1, c)] == 2) ARC(v - cols + 1, H + V + CELL(r - 1, c));
+    if (c > 0) ARC(v - 1, (int64_t)r * (cols - 1) + c - 1);
+    if (c + 1 < cols) ARC(v + 1, (int64_t)r * (cols - 1) + c);
+    if (r + 1 < rows && c > 0 && dg[CELL(r, c - 1)] == 2) ARC(v + cols - 1, H + V + CELL(r, c - 1));
+    if (r + 1 < rows) ARC(v + cols, H + (int64_t)r * cols + c);
+    if (r + 1 < rows && c + 1 < cols && dg[CELL(r, c)] == 1) ARC(v + cols + 1, H + V + CELL(r, c));
+#undef ARC
+  }
+#undef CELL
+  free(dg);
+  out->n = (int32_t)n;
+  out->m = m;
+  out->row_ptr = NULL;
+  out->row_ptr64 = rp;
+  out->col = col;
+  out->w = w;
+  return 0;
+}
+
 /* --------------------------------------------------------------- R-MAT -- */
 
 static void radix_sort_u64(uint64_t *a, uint64_t *tmp, int64_t n, int bits) {
