@@ -56,7 +56,7 @@ const char *cldiam_last_error(void);
 const char *cldiam_version(void);
 
 /* Device CSR of one graph (all DEVICE pointers, caller-owned).
- * n >= 1 nodes, m arcs (m = 2 x edges, m < 2^31). */
+ * n >= 1 nodes (n < 2^31), m arcs (m = 2 x edges, m < 2^40; row offsets are 64-bit). */
 typedef struct {
   int32_t n;
   int32_t pad;
