@@ -24,6 +24,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kSmallRow = 32;     // thread-per-row insertion sort
 constexpr int kLdsRow = 8192;     // block-per-row bitonic sort in LDS
+constexpr int64_t kBatchArcs = (int64_t)1 << 26;   // hub-row arcs sorted together (at least n)
 
 enum : uint32_t {
   BAD_ROWPTR = 1, BAD_COL = 2, BAD_SELF = 4, BAD_ORDER = 8, BAD_WEIGHT = 16, BAD_ASYM = 32,
@@ -136,6 +137,49 @@ __global__ void __launch_bounds__(1024) k_mid_sort(const int64_t *rp, const int3
   }
 }
 
+// Rows longer than kLdsRow arcs are sorted in batches: their arcs are copied
+// side by side (with the row's ordinal in the batch as value), radix-sorted by
+// arc, then stably by ordinal, which regroups every row in place with its
+// arcs in order; a batch holds up to the batch capacity of arcs.
+struct BigRow {
+  int64_t a0;      // first arc of the row
+  uint32_t start;  // its first slot in the batch
+  uint32_t deg;
+};
+
+__global__ void k_big_rows(const int64_t *rp, const int32_t *big, uint32_t nbig, int64_t *out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nbig; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = big[i];
+    out[2 * i] = rp[u];
+    out[2 * i + 1] = rp[u + 1] - rp[u];
+  }
+}
+
+__global__ void k_batch_gather(const uint64_t *arcs, const BigRow *rows, uint32_t nrows, uint64_t *key,
+                               uint64_t *ord) {
+  for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const BigRow b = rows[r];
+    for (uint32_t j = threadIdx.x; j < b.deg; j += blockDim.x) {
+      key[b.start + j] = arcs[b.a0 + j];
+      ord[b.start + j] = r;
+    }
+  }
+}
+
+__global__ void k_batch_scatter(uint64_t *arcs, const BigRow *rows, uint32_t nrows, const uint64_t *key) {
+  for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const BigRow b = rows[r];
+    for (uint32_t j = threadIdx.x; j < b.deg; j += blockDim.x) arcs[b.a0 + j] = key[b.start + j];
+  }
+}
+
+int64_t batch_cap(int32_t n, int64_t m) {
+  const int64_t want = kBatchArcs > (int64_t)n ? kBatchArcs : (int64_t)n;   // every row fits one batch
+  return m + 1 < want ? m + 1 : want;
+}
+
+int64_t big_rows_cap(int64_t m) { return m / (kLdsRow + 1) + 1; }
+
 }  // namespace
 
 extern "C" size_t cldiam_load_csr_workspace_size(int32_t n, int64_t m) {
@@ -144,9 +188,11 @@ extern "C" size_t cldiam_load_csr_workspace_size(int32_t n, int64_t m) {
   s.take<IngestCtl>(1);
   s.take<int32_t>((size_t)n);  // mid rows
   s.take<int32_t>((size_t)n);  // big rows
-  // largest possible big row is < m arcs: key + tmp + radix workspace
-  s.take<uint64_t>((size_t)m + 1);
-  s.used += cld::radix_ws_bytes(m + 1);
+  const int64_t nb = big_rows_cap(m), B = batch_cap(n, m);
+  s.take<int64_t>(2 * (size_t)nb);   // (offset, degree) of every big row
+  s.take<BigRow>((size_t)nb);
+  for (int i = 0; i < 4; ++i) s.take<uint64_t>((size_t)B);   // batch keys, ordinals and their radix buffers
+  s.used += cld::radix_ws_bytes(B);
   return s.used;
 }
 
@@ -163,8 +209,12 @@ extern "C" int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *
   IngestCtl *ctl = a.take<IngestCtl>(1);
   int32_t *mid = a.take<int32_t>((size_t)n);
   int32_t *big = a.take<int32_t>((size_t)n);
-  uint64_t *tmp = a.take<uint64_t>((size_t)m + 1);
-  if (!ctl || !mid || !big || !tmp) {
+  const int64_t nbcap = big_rows_cap(m), B = batch_cap(n, m);
+  int64_t *binfo = a.take<int64_t>(2 * (size_t)nbcap);
+  BigRow *brows = a.take<BigRow>((size_t)nbcap);
+  uint64_t *bk = a.take<uint64_t>((size_t)B), *bo = a.take<uint64_t>((size_t)B);
+  uint64_t *bkt = a.take<uint64_t>((size_t)B), *bot = a.take<uint64_t>((size_t)B);
+  if (!ctl || !mid || !big || !binfo || !brows || !bk || !bo || !bkt || !bot) {
     cld::set_error("load_csr: workspace of %zu bytes, %zu needed", ws_bytes, cldiam_load_csr_workspace_size(n, m));
     return CLDIAM_ENOMEM;
   }
@@ -195,19 +245,49 @@ extern "C" int cldiam_load_csr(const cldiam_csr *g, uint64_t *d_arcs, uint64_t *
       CLD_LAUNCH_CHECK("k_mid_sort");
     }
     if (h.nbig) {
-      std::vector<int32_t> rows(h.nbig);
-      std::vector<int64_t> rp(n + 1);
-      CLD_HIP(hipMemcpyAsync(rows.data(), big, 4 * (size_t)h.nbig, hipMemcpyDeviceToHost, stream));
-      CLD_HIP(hipMemcpyAsync(rp.data(), g->d_row_ptr, 8 * ((size_t)n + 1), hipMemcpyDeviceToHost, stream));
+      if ((int64_t)h.nbig > nbcap) { cld::set_error("load_csr: hub row count out of range"); return CLDIAM_EHIP; }
+      k_big_rows<<<cld::blocks_for(h.nbig, kT, 1024), kT, 0, stream>>>(g->d_row_ptr, big, h.nbig, binfo);
+      CLD_LAUNCH_CHECK("k_big_rows");
+      std::vector<int64_t> info(2 * (size_t)h.nbig);
+      CLD_HIP(hipMemcpyAsync(info.data(), binfo, 16 * (size_t)h.nbig, hipMemcpyDeviceToHost, stream));
       CLD_HIP(hipStreamSynchronize(stream));
-      for (int32_t u : rows) {
-        const int64_t a0 = rp[u], deg = rp[u + 1] - rp[u];
-        bool in_tmp = false;
-        int rc = cld::radix_sort_u64(d_arcs + a0, nullptr, deg, 0, 64, tmp, nullptr, &in_tmp, a.base + a.used,
-                                     a.cap - a.used, stream);
-        if (rc) return rc;
-        if (in_tmp) CLD_HIP(hipMemcpyAsync(d_arcs + a0, tmp, 8 * (size_t)deg, hipMemcpyDeviceToDevice, stream));
+      // batches of whole rows, at most B arcs each (every row has at most n - 1 < B arcs)
+      std::vector<BigRow> desc(h.nbig);
+      std::vector<std::pair<uint32_t, uint32_t>> batches;   // (first row, row count)
+      int64_t fill = 0;
+      uint32_t first = 0;
+      for (uint32_t i = 0; i < h.nbig; ++i) {
+        const int64_t deg = info[2 * i + 1];
+        if (fill + deg > B) {
+          batches.push_back({first, i - first});
+          first = i;
+          fill = 0;
+        }
+        desc[i] = {info[2 * i], (uint32_t)fill, (uint32_t)deg};
+        fill += deg;
       }
+      batches.push_back({first, h.nbig - first});
+      CLD_HIP(hipMemcpyAsync(brows, desc.data(), sizeof(BigRow) * desc.size(), hipMemcpyHostToDevice, stream));
+      for (const auto &bt : batches) {
+        const BigRow &last = desc[bt.first + bt.second - 1];
+        const int64_t total = (int64_t)last.start + last.deg;
+        int ob = 1;
+        while (ob < 64 && (bt.second - 1) >> ob) ++ob;
+        k_batch_gather<<<bt.second < 4096 ? bt.second : 4096, 1024, 0, stream>>>(d_arcs, brows + bt.first,
+                                                                                bt.second, bk, bo);
+        CLD_LAUNCH_CHECK("k_batch_gather");
+        bool t1 = false, t2 = false;
+        int rc = cld::radix_sort_u64(bk, bo, total, 0, 64, bkt, bot, &t1, a.base + a.used, a.cap - a.used, stream);
+        if (rc) return rc;
+        uint64_t *k1 = t1 ? bkt : bk, *o1 = t1 ? bot : bo, *k1t = t1 ? bk : bkt, *o1t = t1 ? bo : bot;
+        // stable by ordinal: the ordinals are the keys now, the arcs ride along
+        rc = cld::radix_sort_u64(o1, k1, total, 0, ob, o1t, k1t, &t2, a.base + a.used, a.cap - a.used, stream);
+        if (rc) return rc;
+        k_batch_scatter<<<bt.second < 4096 ? bt.second : 4096, 1024, 0, stream>>>(d_arcs, brows + bt.first,
+                                                                                 bt.second, t2 ? k1t : k1);
+        CLD_LAUNCH_CHECK("k_batch_scatter");
+      }
+      CLD_HIP(hipStreamSynchronize(stream));   // desc is read by the copies above
     }
   }
   CLD_HIP(hipStreamSynchronize(stream));

@@ -93,6 +93,27 @@ def test_road4096_variants(road, variant):
     assert (phi, approx) == (ref["phi_gc"], ref["phi_approx"])
 
 
+def _check_packed_rows(dg):
+    """Every row of the packed arcs is ascending by (w, col) and holds the
+    same arcs as the input row (per-row sums of col, w and col ^ w), checked
+    on the device for all 521M arcs."""
+    import torch
+    n, m = dg.n, dg.m
+    arcs = dg.arcs[:m]
+    rp = dg.row_ptr
+    deg = rp[1:] - rp[:-1]
+    start = torch.zeros(m, dtype=torch.bool, device=arcs.device)
+    start[rp[:-1][deg > 0]] = True
+    assert bool(((arcs[1:] >= arcs[:-1]) | start[1:]).all()), "a packed row is out of order"
+    row = torch.repeat_interleave(torch.arange(n, device=arcs.device), deg)
+    col, w = arcs & 0xFFFFFFFF, arcs >> 32
+    col0, w0 = dg.col.long(), dg.w.long() & 0xFFFFFFFF
+    for a, b in ((col, col0), (w, w0), (col ^ w, col0 ^ w0)):
+        sa = torch.zeros(n, dtype=torch.int64, device=arcs.device).index_add_(0, row, a)
+        sb = torch.zeros(n, dtype=torch.int64, device=arcs.device).index_add_(0, row, b)
+        assert bool((sa == sb).all()), "a packed row lost or gained arcs"
+
+
 @pytest.mark.timeout(900)
 def test_rmat24_decompose_quotient_estimate():
     import torch
@@ -104,6 +125,8 @@ def test_rmat24_decompose_quotient_estimate():
     assert (g.n, g.m) == (counts["n"], counts["m_arcs"])
     dg = cd.cldiam_load_csr(g)
     del g
+    print("[fullsize] rmat24 ingest order", file=sys.stderr, flush=True)
+    _check_packed_rows(dg)
     print("[fullsize] rmat24 decompose", file=sys.stderr, flush=True)
     cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"])
     assert (st.stages, st.levels, st.delta0, st.delta_end) == \

@@ -117,6 +117,29 @@ def test_ingest_sorts_hub_rows():
     assert np.array_equal(arcs[n - 1:], exp[n - 1:])
 
 
+def test_ingest_sorts_many_hub_rows_together():
+    """300 hub rows of 8,200 to 9,000 arcs each (more than 256 rows in one
+    batch, so the stable regrouping by row takes two radix digits), weights
+    drawn from a small range so that equal weights are ordered by column."""
+    rng = np.random.default_rng(9)
+    hubs, leaves = 300, 20000
+    us, vs, ws = [], [], []
+    for h in range(hubs):
+        deg = int(rng.integers(8200, 9001))
+        nb = rng.choice(leaves, size=deg, replace=False) + hubs
+        us.append(np.full(deg, h))
+        vs.append(nb)
+        ws.append(rng.integers(1, 50, size=deg))
+    g = graphgen.csr_from_edges_np(hubs + leaves, np.concatenate(us), np.concatenate(vs), np.concatenate(ws))
+    _say(f"[parity] ingest {hubs} hub rows, m={g.m}")
+    dg = cd.cldiam_load_csr(g)
+    arcs = cd.u64(dg.arcs)[:g.m]
+    exp = (g.w.astype(np.uint64) << np.uint64(32)) | g.col.astype(np.uint64)
+    for u in range(g.n):
+        s, t = g.row_ptr[u], g.row_ptr[u + 1]
+        assert np.array_equal(arcs[s:t], np.sort(exp[s:t])), f"row {u}"
+
+
 def test_ingest_rejects_asymmetric_csr():
     g = graphgen.grid(6, 6, 10, 1)
     w = g.w.copy()
