@@ -99,7 +99,7 @@ static uint32_t uf_find(uint32_t *p, uint32_t x) {
 typedef struct {
   int32_t n;
   int64_t m; /* arcs = 2 x undirected edges */
-  int32_t *row_ptr; /* n+1; int32 because m < 2^31 for every supported size */
+  int32_t *row_ptr; /* n+1 in int32 (NULL from gg_mesh64, whose offsets pass 2^31) */
   int32_t *col;
   uint32_t *w;
   int64_t *row_ptr64; /* same offsets in int64, always filled */
