@@ -191,14 +191,14 @@ typedef struct {
   int32_t row_bucket_shift; /* nodes whose rows hold more than 32 arcs are relaxed only once their
                            tentative distance is below (smallest distance on the frontier) +
                            Delta / 2^shift, so that long rows are rarely scanned twice in one growth;
-                           0 = default (CLDIAM_ROW_SHIFT_DEFAULT), < 0 = no such bucket; values above
-                           31 act as 31.  Synchronous steps use none. */
+                           0 = default: floor(log2 m) / 2 - 6 clamped to [5, 8] (wider buckets, fewer
+                           sweeps, on small graphs); < 0 = no such bucket; values above 31 act as 31.
+                           Synchronous steps use none. */
   int32_t chunk_factor; /* chunks of a growth sweep per workgroup: the first goes to each workgroup, the
                            rest to whichever workgroup is free next; 0 = default (3 on graphs of more
                            than 2^21 nodes with more than 16 arcs per node, else 1), at most 64 */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
-#define CLDIAM_ROW_SHIFT_DEFAULT 8
 
 /* One graph description of a batch (graph operand in DEVICE memory). */
 typedef struct {

@@ -192,6 +192,8 @@ constexpr int kLocalRoundsDense = 2;   // ... on graphs with more than kDenseDeg
 constexpr int kDenseDegree = 16;       // more than kDenseLarge nodes (none on smaller dense graphs)
 constexpr int32_t kDenseLarge = 1 << 21;
 constexpr int32_t kDenseChunks = 3;     // RELAX / NEXT chunks per workgroup on dense graphs
+constexpr int32_t kRowShiftMin = 5;     // default long-row bucket: Delta >> shift, shift from the arc count
+constexpr int32_t kRowShiftMax = 8;
 constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get kSmallRounds local rounds
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
@@ -1456,8 +1458,14 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
   // and few on dense ones (their rows are long and their growth shallow)
   // long-row bucket: the caller's shift, else the default; none for
   // synchronous steps (their sweeps take every active node)
+  // The default narrows with the graph: a narrower bucket saves rescans of
+  // long rows but costs sweeps, whose fixed cost weighs more on small graphs.
   const int32_t rs = tuning ? tuning->row_bucket_shift : 0;
-  d.row_shift = (rs < 0 || d.variant == CLDIAM_VARIANT_STEPS) ? -1 : (rs == 0 ? CLDIAM_ROW_SHIFT_DEFAULT : (rs > 31 ? 31 : rs));
+  int32_t auto_shift = 0;
+  while (auto_shift < 62 && (x.m >> (auto_shift + 1)) > 0) ++auto_shift;   // floor(log2 m)
+  auto_shift = auto_shift / 2 - 6;
+  auto_shift = auto_shift < kRowShiftMin ? kRowShiftMin : (auto_shift > kRowShiftMax ? kRowShiftMax : auto_shift);
+  d.row_shift = (rs < 0 || d.variant == CLDIAM_VARIANT_STEPS) ? -1 : (rs == 0 ? auto_shift : (rs > 31 ? 31 : rs));
   // large dense graphs: the cost of a chunk varies with the hub rows it
   // holds, so cut their frontiers finer and hand the chunks out on demand
   const int32_t cf = tuning ? tuning->chunk_factor : 0;
