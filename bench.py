@@ -56,6 +56,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_digest(path):
+    """SHA-256 of a source file's code: comments, trailing spaces and blank
+    lines removed, so that stored counters stay tied to the code they were
+    taken on and not to its comments."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
+
+
 def step_bench(args, name):
     import torch
 
@@ -148,15 +160,13 @@ def step_bench(args, name):
                "sample": f"{what} (decompose + quotient + estimate, {tc:.1f} s single-threaded, "
                          f"host {os.cpu_count()} cpus visible)"}
 
-    import hashlib
-    src_sha = hashlib.sha256(open(os.path.join(HERE, "paper_1506_03265_amd", "csrc", "decompose.hip"),
-                                  "rb").read()).hexdigest()
+    src_sha = code_digest(os.path.join(HERE, "paper_1506_03265_amd", "csrc", "decompose.hip"))
     traffic = None
     tpath = os.path.join(HERE, "profiles", f"{name}_traffic.json")
     if os.path.exists(tpath):
         tr = json.load(open(tpath))
-        if tr.get("source_sha256") == src_sha:
-            traffic = tr["traffic_bytes"]   # counters taken on this very kernel source
+        if tr.get("code_sha256") == src_sha:
+            traffic = tr["traffic_bytes"]   # counters taken on this very kernel code
     # random-access view: request counts of one decomposition (counters taken on
     # this kernel source) against the GPU's scattered-access ceilings
     random_access = None
@@ -165,7 +175,7 @@ def step_bench(args, name):
     if os.path.exists(rpath) and os.path.exists(cpath):
         rq = json.load(open(rpath))
         ce = json.load(open(cpath))["config"]
-        if rq.get("source_sha256") == src_sha:
+        if rq.get("code_sha256") == src_sha:
             atom = rq["atomic_with_return"] + rq["atomic_without_return"]
             floor_s = atom / (ce["random_scatter_min_Gops"] * 1e9) + rq["read_requests"] / (ce["random_gather_Gops"] * 1e9)
             random_access = {"atomics": atom, "reads": rq["read_requests"], "writes": rq["write_requests"],

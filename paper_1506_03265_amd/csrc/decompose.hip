@@ -10,11 +10,17 @@
 //
 // and all graphs advance in lock step through "sweeps": in one sweep every
 // graph contributes the items of the list its phase works on (uncovered
-// nodes, frontier, blocked nodes or newly covered nodes), the items of all
-// graphs form one index space, and each workgroup takes one contiguous range
-// of it.  Between sweeps one workgroup runs the per-graph control step (one
-// thread per graph), which applies Algorithm 1's decisions: coverage test,
-// Delta doubling, stage end, termination.
+// nodes, frontier, blocked nodes or newly covered nodes), each graph's items
+// are cut into chunks (one per workgroup, or a few per workgroup on large
+// dense graphs), workgroup b takes chunk b and further chunks go to whichever
+// workgroup asks next.  Between sweeps one workgroup runs the per-graph
+// control step (one thread per graph), which applies Algorithm 1's decisions:
+// coverage test, Delta doubling, stage end, termination.
+//
+// A relaxation sweep takes only frontier nodes whose tentative distance lies
+// in the current distance bucket (a narrower one for nodes with long rows)
+// and keeps the others on the frontier, which orders the label-correcting
+// growth like Delta-stepping without changing its fixpoint.
 //
 // Node state is one u64 key per node: (growth distance << 32) | center id,
 // ~0 when unset.  An offer (d_u + w, c_u) is applied with a 64-bit atomicMin,
