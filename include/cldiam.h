@@ -265,7 +265,12 @@ int cldiam_server_poll(cldiam_server *server, uint64_t *h_tags, cldiam_stats *h_
  *   d_qcol[<= m]      quotient neighbours
  *   d_qw[<= m]        quotient weights (u64)
  * and on the host *h_k = k and *h_qm = number of quotient arcs (2 x edges).
- * Arrays sized n+1 (row_ptr), n (center) and m (col, w) always suffice. */
+ * Arrays sized n+1 (row_ptr), n (center) and m (col, w) always suffice.
+ * d_cluster must label every node with a center (a node c with
+ * d_cluster[c] = c), as cldiam_decompose does; any other labelling returns
+ * CLDIAM_EINVAL before a label is used as an index.  More than 2^32 - 1
+ * distinct cluster pairs after the per-workgroup aggregation return
+ * CLDIAM_EOVERFLOW. */
 size_t cldiam_quotient_workspace_size(int32_t n, int64_t m);
 int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                           const int32_t *d_cluster, const uint64_t *d_D, int32_t *d_qcenter, int64_t *d_qrow_ptr,

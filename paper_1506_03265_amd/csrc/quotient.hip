@@ -31,12 +31,18 @@ struct QCtl {
   uint32_t k;
   uint32_t uniq;    // quotient arcs
   uint32_t wide;    // some D does not fit the packed node word
-  uint32_t pad;
+  uint32_t bad;     // some label is out of range or not a center
 };
 
-__global__ void k_center_flags(const int32_t *cluster, int32_t n, uint32_t *flag) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    flag[v] = cluster[v] == (int32_t)v ? 1u : 0u;
+// Center flags; a label that is out of range or names a node that is not its
+// own center is reported (the caller then gets CLDIAM_EINVAL, no kernel
+// indexes with it).
+__global__ void k_center_flags(const int32_t *cluster, int32_t n, uint32_t *flag, QCtl *ctl) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = cluster[v];
+    flag[v] = c == (int32_t)v ? 1u : 0u;
+    if ((uint32_t)c >= (uint32_t)n || cluster[c] != c) ctl->bad = 1u;
+  }
 }
 
 __device__ __forceinline__ int bits_for_dev(uint32_t x) {  // bits needed for values 0..x, at least 1
@@ -54,8 +60,9 @@ __global__ void k_pack_nodes(const int32_t *cluster, const uint64_t *D, const ui
   const int lb = 64 - bits_for_dev(k > 0 ? k - 1 : 0u);
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t d = D[v];
+    const int32_t c = cluster[v];
     if (d >> lb) ctl->wide = 1u;
-    pk[v] = ((uint64_t)dense[cluster[v]] << lb) | d;
+    pk[v] = (uint32_t)c < (uint32_t)n ? ((uint64_t)dense[c] << lb) | d : 0ull;   // bad labels fail the call
   }
 }
 
@@ -353,7 +360,7 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_
   void *rest = a.base + a.used;
   const size_t rest_bytes = a.cap - a.used;
   CLD_HIP(hipMemsetAsync(ctl, 0, sizeof(QCtl), stream));
-  k_center_flags<<<cld::blocks_for(n, kT, 8192), kT, 0, stream>>>(d_cluster, n, flag);
+  k_center_flags<<<cld::blocks_for(n, kT, 8192), kT, 0, stream>>>(d_cluster, n, flag, ctl);
   CLD_LAUNCH_CHECK("k_center_flags");
   int rc = cld::scan_exclusive_u32(flag, dense, n, &ctl->k, rest, rest_bytes, stream);
   if (rc) return rc;
@@ -366,6 +373,10 @@ extern "C" int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_
   QCtl h;
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
+  if (h.bad) {
+    cld::set_error("build_quotient: a cluster label is out of range or not a center (cluster[c] != c)");
+    return CLDIAM_EINVAL;
+  }
   const int32_t k = (int32_t)h.k;
   const int kb = bits_for(k > 0 ? (uint32_t)(k - 1) : 0u);
   if (m > 0) {

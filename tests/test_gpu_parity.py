@@ -342,3 +342,25 @@ def test_quotient_with_large_distance_bounds(extra):
     assert np.array_equal(q.row_ptr.cpu().numpy(), rrp)
     assert np.array_equal(q.col.cpu().numpy(), rcol)
     assert np.array_equal(cd.u64(q.w), rw)
+
+
+@pytest.mark.parametrize("bad", ["out_of_range", "negative", "not_a_center"])
+def test_quotient_rejects_bad_labels(bad):
+    """A labelling that is not a clustering (a label out of range, or naming a
+    node that is not its own center) is refused with CLDIAM_EINVAL."""
+    import torch
+    g = graphgen.grid_small(1)
+    ref = oracle.decompose(g, 1, 1)
+    cl = ref.cluster.astype(np.int32).copy()
+    u, v = (int(x) for x in np.nonzero(cl != np.arange(g.n))[0][:2])   # two nodes that are not centers
+    if bad == "out_of_range":
+        cl[u] = g.n + 5
+    elif bad == "negative":
+        cl[u] = -1
+    else:
+        cl[u] = v   # u's label names v, which is not its own center
+    _say(f"[parity] quotient bad labels {bad}")
+    dg = cd.cldiam_load_csr(g)
+    with pytest.raises(cd.CldiamError) as e:
+        cd.cldiam_build_quotient(dg, torch.from_numpy(cl).cuda(), torch.from_numpy(ref.D.view(np.int64)).cuda())
+    assert e.value.status == cd.CLDIAM_EINVAL
