@@ -281,7 +281,9 @@ int cldiam_build_quotient(int32_t n, int64_t m, const int64_t *d_row_ptr, const 
  * Phi(G_C) = exact largest finite shortest-path distance between two nodes of
  * the quotient graph (k nodes, symmetric CSR from cldiam_build_quotient), and
  * Phi_approx = Phi(G_C) + 2 radius, the conservative estimate of Section 4
- * (radius = max D of the decomposition).  Results on the host. */
+ * (radius = max D of the decomposition).  Results on the host.  Row offsets
+ * that do not run from 0 to qm without decreasing, or a column outside
+ * [0, k), return CLDIAM_EINVAL before the CSR is traversed. */
 size_t cldiam_estimate_workspace_size(int32_t k, int64_t qm);
 int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, const int32_t *d_qcol,
                              const uint64_t *d_qw, uint64_t radius, uint64_t *h_phi_gc, uint64_t *h_phi_approx,

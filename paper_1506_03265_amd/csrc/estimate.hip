@@ -16,7 +16,23 @@ constexpr int kLdsMaxK = 3072;  // 20 bytes per node -> 60 KB
 
 struct ECtl {
   unsigned long long phi;
+  uint32_t bad;   // the quotient CSR is malformed: nothing is indexed with it
+  uint32_t pad;
 };
+
+// The quotient CSR must have row offsets from 0 to qm, non-decreasing, and
+// columns in [0, k); anything else fails the call before the APSP reads it.
+__global__ void k_check_quotient(int32_t k, int64_t qm, const int64_t *rp, const int32_t *col, uint32_t *bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+    bool ok = rp[i] <= rp[i + 1];
+    if (i == 0) ok = ok && rp[0] == 0;
+    if (i == k - 1) ok = ok && rp[k] == qm;
+    if (!ok) *bad = 1u;
+  }
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < qm; a += stride)
+    if ((uint32_t)col[a] >= (uint32_t)k) *bad = 1u;
+}
 
 __device__ void sssp_block(int32_t k, const int64_t *rp, const int32_t *col, const uint64_t *w, int32_t s,
                            uint64_t *dist, uint32_t *stamp, int32_t *q0, int32_t *q1, uint64_t *phi) {
@@ -60,7 +76,8 @@ __device__ void sssp_block(int32_t k, const int64_t *rp, const int32_t *col, con
 }
 
 __global__ void __launch_bounds__(kT) k_apsp_lds(int32_t k, const int64_t *rp, const int32_t *col,
-                                                 const uint64_t *w, uint64_t *phi) {
+                                                 const uint64_t *w, uint64_t *phi, const uint32_t *bad) {
+  if (*bad) return;
   extern __shared__ uint64_t lds[];
   uint64_t *dist = lds;
   uint32_t *stamp = (uint32_t *)(dist + k);
@@ -70,7 +87,9 @@ __global__ void __launch_bounds__(kT) k_apsp_lds(int32_t k, const int64_t *rp, c
 }
 
 __global__ void __launch_bounds__(kT) k_apsp_global(int32_t k, const int64_t *rp, const int32_t *col,
-                                                    const uint64_t *w, uint64_t *phi, char *scratch) {
+                                                    const uint64_t *w, uint64_t *phi, char *scratch,
+                                                    const uint32_t *bad) {
+  if (*bad) return;
   const size_t per = (size_t)k * 20;
   char *base = scratch + per * blockIdx.x;
   uint64_t *dist = (uint64_t *)base;
@@ -110,15 +129,24 @@ extern "C" int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_
     return CLDIAM_ENOMEM;
   }
   CLD_HIP(hipMemsetAsync(ctl, 0, sizeof(ECtl), stream));
+  k_check_quotient<<<cld::blocks_for(k > qm ? (int64_t)k : qm, kT, 1024), kT, 0, stream>>>(k, qm, d_qrow_ptr,
+                                                                                           d_qcol, &ctl->bad);
+  CLD_LAUNCH_CHECK("k_check_quotient");
   if (k <= kLdsMaxK) {
-    k_apsp_lds<<<grid_for(k), kT, (size_t)k * 20, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi);
+    k_apsp_lds<<<grid_for(k), kT, (size_t)k * 20, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi,
+                                                           &ctl->bad);
   } else {
-    k_apsp_global<<<grid_for(k), kT, 0, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi, scratch);
+    k_apsp_global<<<grid_for(k), kT, 0, stream>>>(k, d_qrow_ptr, d_qcol, d_qw, (uint64_t *)&ctl->phi, scratch,
+                                                  &ctl->bad);
   }
   CLD_LAUNCH_CHECK("k_apsp");
   ECtl h;
   CLD_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, stream));
   CLD_HIP(hipStreamSynchronize(stream));
+  if (h.bad) {
+    cld::set_error("estimate_diameter: malformed quotient CSR (row offsets or a column out of range)");
+    return CLDIAM_EINVAL;
+  }
   *h_phi_gc = h.phi;
   *h_phi_approx = h.phi + 2 * radius;
   return CLDIAM_OK;

@@ -364,3 +364,29 @@ def test_quotient_rejects_bad_labels(bad):
     with pytest.raises(cd.CldiamError) as e:
         cd.cldiam_build_quotient(dg, torch.from_numpy(cl).cuda(), torch.from_numpy(ref.D.view(np.int64)).cuda())
     assert e.value.status == cd.CLDIAM_EINVAL
+
+
+@pytest.mark.parametrize("bad", ["column", "offsets", "last_offset"])
+def test_estimate_rejects_malformed_quotient(bad):
+    """A quotient CSR with a column outside [0, k) or row offsets that do not
+    run from 0 to qm without decreasing is refused with CLDIAM_EINVAL."""
+    import torch
+    g = graphgen.grid_small(1)
+    _say(f"[parity] estimate malformed {bad}")
+    dg = cd.cldiam_load_csr(g)
+    c, D, st = cd.cldiam_decompose(dg, 1, 1)
+    q = cd.cldiam_build_quotient(dg, c, D)
+    rp, col, w = q.row_ptr.clone(), q.col.clone(), q.w.clone()
+    if bad == "column":
+        col[3] = q.k
+    elif bad == "offsets":
+        rp[1], rp[2] = rp[2].clone(), rp[1].clone()
+        if int(rp[1]) == int(rp[2]):
+            rp[1] += 1
+    else:
+        rp[-1] += 1
+    fake = cd.DeviceQuotient(q.k, q.qm, q.center, rp, col, w)
+    with pytest.raises(cd.CldiamError) as e:
+        cd.cldiam_estimate_diameter(fake, st.radius)
+    assert e.value.status == cd.CLDIAM_EINVAL
+    assert cd.cldiam_estimate_diameter(q, st.radius)[0] > 0   # the untouched quotient still works
