@@ -71,6 +71,23 @@ def test_chunk_factor_on_long_rows(chunk_factor, grid_blocks, driver):
     assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
 
 
+@pytest.mark.parametrize("scale,gseed", [(10, 1), (12, 2), (14, 3), (16, 1)])
+def test_rmat_family_under_two_schedules(scale, gseed):
+    """R-MAT graphs of several sizes and seeds, CLUSTER and CLUSTER2, under the
+    default schedule and under on-demand chunks on an odd grid: the oracle's
+    outputs every time."""
+    g = graphgen.rmat(scale, seed=gseed)
+    dg = cd.cldiam_load_csr(g)
+    _say(f"[systems] rmat{scale} seed {gseed} schedules")
+    for tau, seed in ((1, 7), (4, 3)):
+        for variant in (cd.VARIANT_FIXPOINT, cd.VARIANT_CLUSTER2):
+            ref = oracle.decompose_cluster2(g, tau, seed) if variant else oracle.decompose(g, tau, seed)
+            for cf, blocks in ((0, 0), (3, 97)):
+                c, D, st = cd.cldiam_decompose(dg, tau, seed, variant=variant, chunk_factor=cf, grid_blocks=blocks)
+                assert np.array_equal(c.cpu().numpy(), ref.cluster), (tau, seed, variant, cf)
+                assert np.array_equal(cd.u64(D), ref.D), (tau, seed, variant, cf)
+
+
 def test_batch_of_geometric_graphs_matches_oracle():
     sizes = [1000, 1500, 2500, 4000, 7000, 12000, 20000, 30000] * 3
     graphs = [graphgen.rgg(n, i, 5) for i, n in enumerate(sizes)]
