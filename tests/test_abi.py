@@ -95,3 +95,20 @@ def test_python_structures_match_the_header(tmp_path):
         assert ctypes.sizeof(py) == got[(cname, "size")], cname
         for f in names or []:
             assert getattr(py, f).offset == got[(cname, f)], (cname, f)
+
+
+def test_c_example_builds_against_the_header(tmp_path):
+    """The plain-C example that drives the whole path through the ABI
+    (ingest, decomposition, quotient, estimate) compiles and links with gcc."""
+    import shutil
+    import subprocess
+    rocm = "/opt/rocm"
+    lib_dir = os.path.join(ROOT, "paper_1506_03265_amd")
+    if not os.path.exists(os.path.join(lib_dir, "libcldiam.so")) or not os.path.exists(rocm) or not shutil.which("gcc"):
+        pytest.skip("needs libcldiam.so, ROCm headers and gcc")
+    exe = tmp_path / "diameter"
+    subprocess.check_call(["gcc", "-std=c11", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"),
+                           os.path.join(lib_dir, "examples", "diameter.c"), "-o", str(exe),
+                           "-L", lib_dir, "-lcldiam", "-L", os.path.join(rocm, "lib"), "-lamdhip64"])
+    assert exe.exists()
