@@ -188,13 +188,51 @@ def cluster(n, edges, tau, seed, delta0=0, mode="apsp"):
                 radius=max(D) if D else 0, levels=levels)
 
 
-def partial_growth_steps(nodes, adj, delta, state, U, covered0, step_cap=0):
+class MessageCount:
+    """Counts the messages of the literal steps over the ORIGINAL graph (the
+    paper's work counter: offers sent), independently of how the growth is
+    computed.  In a step the active set A sends one offer over every original
+    arc (u, v, w) with d_u + w <= Delta, where d_u is 0 for a node assigned in
+    an earlier stage (Procedure Contract makes it part of its center) and its
+    current distance otherwise.  A is the set of nodes updated by the previous
+    step; the new centers join it when a stage starts; the nodes that sent at
+    some step of the current Delta and had an arc with d_u + w > Delta (set B)
+    join it whenever Delta doubles and when a stage ends (they may offer at the
+    next Delta or, assigned, in the next stage)."""
+
+    def __init__(self, n, edges):
+        self.adj = {v: [] for v in range(n)}
+        for u, v, w in edges:
+            self.adj[u].append(w)
+            self.adj[v].append(w)
+        self.assigned = set()
+        self.A, self.B = set(), set()
+        self.messages = 0
+
+    def step(self, state, delta):
+        for u in self.A:
+            du = 0 if u in self.assigned else state[u][0]
+            assert du != INF, "an active node has a distance"
+            for w in self.adj[u]:
+                if du + w <= delta:
+                    self.messages += 1
+                else:
+                    self.B.add(u)
+
+    def release_blocked(self):
+        self.A |= self.B
+        self.B = set()
+
+
+def partial_growth_steps(nodes, adj, delta, state, U, covered0, step_cap=0, msg=None):
     """Procedure PartialGrowth of Algorithm 1 taken literally: synchronous
     Delta-growing steps (every node u with d_u < Delta offers d_u + w to each
     neighbour over an edge with d_u + w <= Delta; v accepts only a strictly
     smaller distance, the smallest center winning among the offers of one
     step), repeated until a step updates no state or at least half of the
     uncovered nodes U have d <= Delta, or after step_cap steps (0 = no cap).
+    With a MessageCount, every step's messages are counted before its offers
+    are applied, and the step's updated nodes become its active set.
 
     Returns (steps executed, node updates, number of U nodes with d <= Delta,
     whether the last step updated some state)."""
@@ -204,6 +242,8 @@ def partial_growth_steps(nodes, adj, delta, state, U, covered0, step_cap=0):
     if 2 * covered >= len(U):
         return steps, updates, covered, False
     while True:
+        if msg is not None:
+            msg.step(state, delta)
         offers = {}
         for u in nodes:
             du, cu = state[u]
@@ -221,6 +261,8 @@ def partial_growth_steps(nodes, adj, delta, state, U, covered0, step_cap=0):
                 covered += 1
             state[v] = cand
         updates += len(offers)
+        if msg is not None:
+            msg.A = set(offers)
         if not offers or 2 * covered >= len(U) or (step_cap and steps >= step_cap):
             return steps, updates, covered, bool(offers)
 
@@ -234,7 +276,7 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
     node is reachable from the clusters at any Delta.
 
     Returns dict(cluster, D, stages, delta_end, num_clusters, radius, levels,
-    rounds, updates)."""
+    rounds, updates, messages)."""
     gamma = 4.0 * math.log(2.0)
     L = math.log2(n)
     stop = math.ceil(8.0 * tau * L)
@@ -253,6 +295,7 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
     D = [0] * n
     R = [0] * n
     s = levels = rounds = updates = 0
+    msg = MessageCount(n, edges)
     while True:
         U = sorted(Vi - Ci)
         if n < 2 or not U or len(U) < stop:
@@ -264,9 +307,10 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
         state = {v: ((0, v) if v in X else (INF, None)) for v in Vi}
         nodes = sorted(Vi)
         covered = len(new)
+        msg.A |= set(new)
         while 2 * covered < len(U):
             levels += 1
-            k, up, covered, moved = partial_growth_steps(nodes, adj, delta, state, U, covered, step_cap)
+            k, up, covered, moved = partial_growth_steps(nodes, adj, delta, state, U, covered, step_cap, msg)
             rounds += k
             updates += up
             if 2 * covered >= len(U):
@@ -277,6 +321,7 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
             if 2 * delta > (1 << 31):
                 raise OverflowError("Delta above 2^31")
             delta *= 2
+            msg.release_blocked()
         got = [v for v in U if state[v][0] <= delta]
         for v in got:
             c = state[v][1]
@@ -284,6 +329,8 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
             D[v] = state[v][0] + R[c]
         for v in got:
             R[cluster_of[v]] = max(R[cluster_of[v]], D[v])
+        msg.assigned |= set(got)
+        msg.release_blocked()
         clustered = set(X) | set(got)
         label = {v: (v if v in X else state[v][1]) for v in clustered}
         nadj = {v: {} for v in Vi if v not in clustered or v in X}
@@ -309,7 +356,8 @@ def cluster_steps(n, edges, tau, seed, delta0=0, step_cap=0):
         D[v] = 0
     return dict(cluster=cluster_of, D=D, stages=s, delta_end=delta,
                 num_clusters=sum(1 for v in range(n) if cluster_of[v] == v),
-                radius=max(D) if D else 0, levels=levels, rounds=rounds, updates=updates)
+                radius=max(D) if D else 0, levels=levels, rounds=rounds, updates=updates,
+                messages=msg.messages)
 
 
 def cluster2(n, edges, tau, seed, delta0=0):

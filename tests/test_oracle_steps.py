@@ -7,8 +7,8 @@ The C oracle (implicit Contract, frontier of updated nodes) must equal the
 brute force that builds every contracted graph with Procedure Contract and in
 every step lets every node with d_u < Delta offer over all its light edges:
 same clusters, distance bounds, stages, Delta, PartialGrowth calls, steps
-(rounds) and node updates.  Messages follow the oracle's own definition; they
-are pinned by invariants."""
+(rounds), node updates and messages.  The brute force counts messages on its
+own, over the original graph's arcs, from the explicit state of each step."""
 import numpy as np
 import pytest
 
@@ -26,6 +26,7 @@ def _same(dec, ref, name):
         (ref["stages"], ref["delta_end"], ref["num_clusters"], int(ref["radius"]), ref["levels"]), name
     assert dec.work["rounds"] == ref["rounds"], name
     assert dec.work["updates"] == ref["updates"], name
+    assert dec.work["messages"] == ref["messages"], name
 
 
 @pytest.mark.parametrize("name,g", FAMILIES, ids=[f for f, _ in FAMILIES])
