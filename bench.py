@@ -341,7 +341,7 @@ def _sssp_lower_bound(cd, dg, src, sweeps=4):
     import torch
     lb, s = 0, src
     for _ in range(sweeps):
-        dist, mx = cd.cldiam_sssp_delta_stepping(dg, s, cd.default_bucket_delta(dg))
+        dist, mx = cd.cldiam_sssp_delta_stepping(dg, s, 0)
         lb = max(lb, int(mx))
         d = dist.to(torch.int64) & 0xFFFFFFFF
         d[d == 0xFFFFFFFF] = -1
@@ -632,7 +632,7 @@ def sssp_bench(args):
     import oracle   # only for the source rule shared with the tests (a Philox draw) and the CPU baseline
     src = oracle.sssp_source(g.n, counts["seed"])
     widths = [int(x) for x in args.bucket_widths.split(",")] if args.bucket_widths else \
-        [cd.default_bucket_delta(dg) // 16 * f for f in (1, 4, 16, 64, 256)]
+        [max(1, dg.weight_sum // max(dg.m, 1)) * f for f in (1, 4, 16, 64, 256)]
     rows = []
     best = None
     for bd in widths:

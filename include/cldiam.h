@@ -54,6 +54,10 @@ const char *cldiam_strerror(int status);
 const char *cldiam_last_error(void);
 /* Library version string. */
 const char *cldiam_version(void);
+/* Pinned host memory held by the library (bytes): small readback buffers that
+ * calls take from a pool and give back when they return, so it grows only with
+ * the number of calls in flight at the same time. */
+int64_t cldiam_pinned_host_bytes(void);
 
 /* Device CSR of one graph (all DEVICE pointers, caller-owned).
  * n >= 1 nodes (n < 2^31), m arcs (m = 2 x edges, m < 2^40; row offsets are 64-bit). */
@@ -294,8 +298,10 @@ int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, c
  * baseline of Section 5: twice the largest finite distance from one source is
  * a 2-approximation of the diameter.  d_dist[v] receives the exact distance
  * (0xFFFFFFFF = unreachable); *h_max_dist the largest finite one.
- * bucket_delta = 0 picks the default width (the mean arc weight).  A finite
- * distance >= 0xFFFFFFFF returns CLDIAM_EOVERFLOW. */
+ * bucket_delta = 0 picks the default width: 16 x floor(sum of arc weights /
+ * m), at least 1 and at most 2^31 (1 on a graph without arcs), computed on
+ * the device from d_arcs.  A finite distance >= 0xFFFFFFFF returns
+ * CLDIAM_EOVERFLOW. */
 size_t cldiam_sssp_workspace_size(int32_t n, int64_t m);
 int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int64_t *d_row_ptr, const uint64_t *d_arcs,
                                int32_t source, uint32_t bucket_delta, uint32_t *d_dist, uint64_t *h_max_dist,

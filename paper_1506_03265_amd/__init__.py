@@ -31,7 +31,7 @@ DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 VARIANT_FIXPOINT, VARIANT_STEPS, VARIANT_CLUSTER2 = 0, 1, 2
 
 EXPORTS = [
-    "cldiam_strerror", "cldiam_last_error", "cldiam_version",
+    "cldiam_strerror", "cldiam_last_error", "cldiam_version", "cldiam_pinned_host_bytes",
     "cldiam_load_csr_workspace_size", "cldiam_load_csr",
     "cldiam_decompose_workspace_size", "cldiam_decompose_batch", "cldiam_decompose",
     "cldiam_quotient_workspace_size", "cldiam_build_quotient",
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     lib.cldiam_strerror.argtypes, lib.cldiam_strerror.restype = [ctypes.c_int], ctypes.c_char_p
     lib.cldiam_last_error.argtypes, lib.cldiam_last_error.restype = [], ctypes.c_char_p
     lib.cldiam_version.argtypes, lib.cldiam_version.restype = [], ctypes.c_char_p
+    lib.cldiam_pinned_host_bytes.argtypes, lib.cldiam_pinned_host_bytes.restype = [], I64
     lib.cldiam_load_csr_workspace_size.argtypes, lib.cldiam_load_csr_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_load_csr.argtypes = [P(_Csr), V, P(U64), V, SZ, V]
     lib.cldiam_decompose_workspace_size.argtypes, lib.cldiam_decompose_workspace_size.restype = [I64, I32], SZ
@@ -431,22 +432,16 @@ def cldiam_estimate_diameter(q: DeviceQuotient, radius: int, stream=None):
 
 # ----------------------------------------------------------------- SSSP --
 
-def default_bucket_delta(g: DeviceGraph) -> int:
-    """Bucket width used when none is given: 16 x the mean arc weight."""
-    mean = g.weight_sum // g.m if g.m else 1
-    return int(max(1, min(16 * mean, 2**31)))
-
-
 def cldiam_sssp_delta_stepping(g: DeviceGraph, source: int, bucket_delta: int = 0, stream=None):
-    """(dist int32 tensor holding uint32 bit patterns, max finite distance)."""
+    """(dist int32 tensor holding uint32 bit patterns, max finite distance).
+    bucket_delta = 0 lets the library pick its default width."""
     torch = _torch()
     lib = load_library()
     dist = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
     wsb = lib.cldiam_sssp_workspace_size(g.n, g.m)
     ws = _ws(wsb, g.row_ptr.device)
     mx = ctypes.c_uint64()
-    bd = bucket_delta or default_bucket_delta(g)
-    _check(lib.cldiam_sssp_delta_stepping(g.n, g.m, _ptr(g.row_ptr), _ptr(g.arcs), source, bd, _ptr(dist),
+    _check(lib.cldiam_sssp_delta_stepping(g.n, g.m, _ptr(g.row_ptr), _ptr(g.arcs), source, bucket_delta, _ptr(dist),
                                           ctypes.byref(mx), _ptr(ws), wsb, _stream(stream)),
            "cldiam_sssp_delta_stepping")
     return dist, int(mx.value)

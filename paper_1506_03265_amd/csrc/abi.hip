@@ -2,9 +2,45 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <atomic>
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 
 namespace cld {
+
+// Pinned host buffers for the small device-to-host readbacks of the host
+// loops.  A call takes one for its duration and gives it back, so the pool
+// grows only to the largest number of calls in flight at once and every
+// buffer is reused (no allocation per call or per thread).
+namespace {
+std::mutex g_pinned_mu;
+std::vector<void *> g_pinned_free;
+std::atomic<int64_t> g_pinned_bytes{0};
+}  // namespace
+
+void *pinned_acquire(size_t bytes) {
+  if (bytes > kPinnedBytes) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      void *p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, kPinnedBytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  g_pinned_bytes += (int64_t)kPinnedBytes;
+  return p;
+}
+
+void pinned_release(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free.push_back(p);
+}
 
 static thread_local char t_err[512] = "";
 
@@ -51,3 +87,5 @@ extern "C" const char *cldiam_strerror(int status) {
 extern "C" const char *cldiam_last_error(void) { return cld::t_err; }
 
 extern "C" const char *cldiam_version(void) { return "cldiam 0.1 gfx950"; }
+
+extern "C" int64_t cldiam_pinned_host_bytes(void) { return cld::g_pinned_bytes.load(); }

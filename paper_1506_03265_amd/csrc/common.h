@@ -50,6 +50,22 @@ struct Sizer {
   void take(size_t count) { used += (count * sizeof(T) + 255) & ~(size_t)255; }
 };
 
+// Pooled pinned host buffers of kPinnedBytes for readbacks (nullptr when the
+// request is larger or the allocation fails); give each one back after use.
+constexpr size_t kPinnedBytes = 4096;
+void *pinned_acquire(size_t bytes);
+void pinned_release(void *p);
+
+// Holds a pooled pinned buffer for the lifetime of a call.
+template <class T>
+struct Pinned {
+  T *p;
+  Pinned() : p((T *)pinned_acquire(sizeof(T))) {}
+  ~Pinned() { pinned_release(p); }
+  Pinned(const Pinned &) = delete;
+  Pinned &operator=(const Pinned &) = delete;
+};
+
 inline int blocks_for(int64_t items, int threads, int cap = 1 << 20) {
   int64_t b = (items + threads - 1) / threads;
   if (b < 1) b = 1;

@@ -1400,16 +1400,7 @@ struct PtrArena {
   void *take(size_t n) { return (void *)a.take<T>(n); }
 };
 
-thread_local Ctl *t_host_ctl = nullptr;
-
-Ctl *host_ctl() {
-  if (!t_host_ctl) {
-    void *p = nullptr;
-    if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return nullptr;
-    t_host_ctl = (Ctl *)p;
-  }
-  return t_host_ctl;
-}
+static_assert(sizeof(Ctl) <= cld::kPinnedBytes, "control block must fit a pooled pinned buffer");
 
 // Workgroups of the sweep grid: one per CU unless requested (bounded by the
 // co-resident maximum for the persistent kernel).
@@ -1599,7 +1590,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   if (!persistent && blocks <= 0) blocks = 256;
   if (blocks > 65535) blocks = 65535;
   job.nblocks = blocks;
-  Ctl *hc = host_ctl();
+  cld::Pinned<Ctl> pinned;   // readback buffer, back to the pool when the call returns
+  Ctl *hc = pinned.p;
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   CLD_HIP(hipEventCreate(&ev0));

@@ -243,6 +243,20 @@ __global__ void __launch_bounds__(kT) k_sssp_max(const uint32_t *dist, int32_t n
   if ((threadIdx.x & 63) == 0 && m) atomicMax(mx, m);
 }
 
+// Sum of all arc weights (the high words of the packed arcs), for the default
+// bucket width.
+__global__ void __launch_bounds__(kT) k_sssp_weight_sum(const uint64_t *arcs, int64_t m, unsigned long long *sum) {
+  unsigned long long s = 0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m; a += (int64_t)gridDim.x * blockDim.x)
+    s += arcs[a] >> 32;
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(sum, s);
+}
+
+// Default bucket width: kDefaultWidth mean arc weights (at least 1, at most
+// 2^31); 1 on a graph without arcs.
+constexpr uint64_t kDefaultWidth = 16;
+
 }  // namespace
 
 extern "C" size_t cldiam_sssp_workspace_size(int32_t n, int64_t m) {
@@ -260,9 +274,8 @@ extern "C" int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int64_t *d
                                           int32_t source, uint32_t bucket_delta, uint32_t *d_dist,
                                           uint64_t *h_max_dist, void *ws, size_t ws_bytes, void *stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  if (n < 1 || m < 0 || source < 0 || source >= n || !d_row_ptr || (m && !d_arcs) || !d_dist || !h_max_dist ||
-      bucket_delta == 0) {
-    cld::set_error("sssp: invalid arguments (bucket_delta must be >= 1)");
+  if (n < 1 || m < 0 || source < 0 || source >= n || !d_row_ptr || (m && !d_arcs) || !d_dist || !h_max_dist) {
+    cld::set_error("sssp: invalid arguments");
     return CLDIAM_EINVAL;
   }
   cld::Arena a(ws, ws_bytes);
@@ -280,6 +293,23 @@ extern "C" int cldiam_sssp_delta_stepping(int32_t n, int64_t m, const int64_t *d
   if (!j.Far[1]) {
     cld::set_error("sssp: workspace of %zu bytes, %zu needed", ws_bytes, cldiam_sssp_workspace_size(n, m));
     return CLDIAM_ENOMEM;
+  }
+  if (bucket_delta == 0) {
+    // default width from the mean arc weight (mx serves as the sum's slot)
+    uint64_t wsum = 0;
+    if (m > 0) {
+      CLD_HIP(hipMemsetAsync(mx, 0, 8, stream));
+      k_sssp_weight_sum<<<cld::blocks_for(m, kT, 4096), kT, 0, stream>>>(d_arcs, m, mx);
+      CLD_LAUNCH_CHECK("k_sssp_weight_sum");
+      unsigned long long hs = 0;
+      CLD_HIP(hipMemcpyAsync(&hs, mx, 8, hipMemcpyDeviceToHost, stream));
+      CLD_HIP(hipStreamSynchronize(stream));
+      wsum = hs;
+    }
+    uint64_t b = m > 0 ? kDefaultWidth * (wsum / (uint64_t)m) : 1;
+    if (b < 1) b = 1;
+    if (b > CLD_DELTA_MAX) b = CLD_DELTA_MAX;
+    bucket_delta = (uint32_t)b;
   }
   j.rp = d_row_ptr;
   j.arcs = d_arcs;

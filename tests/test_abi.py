@@ -62,6 +62,18 @@ def test_invalid_arguments_fail_before_touching_a_device(lib):
     assert lib.cldiam_sssp_delta_stepping(10, 0, None, None, 0, 1, None, None, None, 0, None) == cd.CLDIAM_EINVAL
 
 
+def test_sssp_accepts_the_default_width_marker(lib):
+    """bucket_delta = 0 selects the library's default width; it is not an
+    argument error (an invalid source still is)."""
+    assert lib.cldiam_sssp_delta_stepping(10, 0, None, None, 0, 0, None, None, None, 0, None) == cd.CLDIAM_EINVAL
+    assert b"bucket" not in lib.cldiam_last_error()
+
+
+def test_pinned_host_bytes_is_a_pool_of_whole_buffers(lib):
+    b = lib.cldiam_pinned_host_bytes()
+    assert b >= 0 and b % 4096 == 0
+
+
 def test_python_structures_match_the_header(tmp_path):
     """The ctypes mirrors of the header's structures have the C compiler's
     sizes and field offsets (a plain C program including cldiam.h prints them)."""

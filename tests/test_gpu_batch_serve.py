@@ -144,6 +144,24 @@ def test_served_results_equal_alone_results():
     assert all(r.latency_s >= 0 for r in mixed)
 
 
+def test_pinned_readback_buffers_stay_bounded():
+    """Every request of the stream pool runs on a fresh host thread; the
+    pinned readback buffers are pooled, so 64 served requests with at most 4
+    in flight leave at most 4 more buffers behind (none are leaked per thread)."""
+    from paper_1506_03265_amd import serve
+    lib = cd.load_library()
+    g = graphgen.grid(64, 64, 1000, 5)
+    pool = {"g": cd.cldiam_load_csr(g)}
+    cd.cldiam_decompose(pool["g"], 1, 1)   # the pool holds at least one buffer from here on
+    before = lib.cldiam_pinned_host_bytes()
+    reqs = [serve.Request(i, 0.0, "g", 1, i) for i in range(64)]
+    _say("[systems] 64 requests on fresh threads, pinned pool size")
+    res, _ = serve.serve(reqs, pool, workers=4)
+    assert len(res) == 64
+    after = lib.cldiam_pinned_host_bytes()
+    assert after - before <= 4 * 4096, (before, after)
+
+
 def test_serving_respects_a_tiny_budget():
     """With a budget below two footprints, requests run one at a time and
     still all complete with the same results."""

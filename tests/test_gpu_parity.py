@@ -254,7 +254,8 @@ def test_estimate_global_memory_path():
                                            ("road512", lambda: graphgen.road_like(512, 3), 0),
                                            ("rmat13", lambda: graphgen.rmat(13, seed=2), 0),
                                            ("rmat13_big", lambda: graphgen.rmat(13, seed=2), 2**22),
-                                           ("twocomp", lambda: _GRAPHS["twocomp"], 0), ("star", lambda: _GRAPHS["star"], 0)],
+                                           ("twocomp", lambda: _GRAPHS["twocomp"], 0), ("star", lambda: _GRAPHS["star"], 0),
+                                           ("noedges", lambda: _GRAPHS["noedges"], 0)],
                          ids=lambda x: x if isinstance(x, str) else "")
 def test_sssp_equals_dijkstra(name, maker, bd):
     g = maker()
@@ -265,6 +266,35 @@ def test_sssp_equals_dijkstra(name, maker, bd):
     rd, rmx = oracle.sssp(g, src)
     assert np.array_equal(cd.u32(dist), rd)
     assert mx == rmx
+
+
+def test_sssp_default_width_through_the_abi():
+    """bucket_delta = 0 passed straight to the C entry point runs with the
+    documented default (16 x floor(mean arc weight)): same distances as an
+    explicit call with that width and as Dijkstra."""
+    import ctypes
+    import torch
+    g = graphgen.road_like(200, 4)
+    dg = cd.cldiam_load_csr(g)
+    lib = cd.load_library()
+    src = oracle.sssp_source(g.n, 1)
+    _say(f"[parity] sssp default width through the ABI, src={src}")
+    out = []
+    for bd in (0, 16 * (dg.weight_sum // dg.m)):
+        dist = torch.empty(g.n, dtype=torch.int32, device=dg.row_ptr.device)
+        wsb = lib.cldiam_sssp_workspace_size(g.n, g.m)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dg.row_ptr.device)
+        mx = ctypes.c_uint64()
+        rc = lib.cldiam_sssp_delta_stepping(g.n, g.m, ctypes.c_void_p(dg.row_ptr.data_ptr()),
+                                            ctypes.c_void_p(dg.arcs.data_ptr()), src, bd,
+                                            ctypes.c_void_p(dist.data_ptr()), ctypes.byref(mx),
+                                            ctypes.c_void_p(ws.data_ptr()), wsb,
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == cd.CLDIAM_OK, lib.cldiam_last_error()
+        out.append((cd.u32(dist), mx.value))
+    rd, rmx = oracle.sssp(g, src)
+    for d, mx in out:
+        assert np.array_equal(d, rd) and mx == rmx
 
 
 # ---------------------------------------------------------------- batched --
