@@ -60,22 +60,22 @@ def _load():
             build_lib()
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.POINTER
-        i32p, u32p, u64p = P(ctypes.c_int32), P(ctypes.c_uint32), P(ctypes.c_uint64)
+        i32p, u32p, u64p, i64p = P(ctypes.c_int32), P(ctypes.c_uint32), P(ctypes.c_uint64), P(ctypes.c_int64)
         lib.or_philox.argtypes = [u32p, u32p, u32p]
         lib.or_default_delta.argtypes = [ctypes.c_int64, u32p]
         lib.or_default_delta.restype = ctypes.c_uint32
-        lib.or_decompose.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+        lib.or_decompose.argtypes = [ctypes.c_int32, i64p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.c_uint64, i32p, u64p, P(_Stats), P(_Log)]
-        lib.or_decompose_steps.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+        lib.or_decompose_steps.argtypes = [ctypes.c_int32, i64p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint64, ctypes.c_uint32, i32p, u64p, P(_Stats), P(_StepStats),
                                            P(_Log)]
-        lib.or_decompose_cluster2.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+        lib.or_decompose_cluster2.argtypes = [ctypes.c_int32, i64p, i32p, u32p, ctypes.c_uint32, ctypes.c_uint32,
                                               ctypes.c_uint64, i32p, u64p, P(_Stats), u64p, P(_Log)]
-        lib.or_quotient.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, u64p, i32p, P(i32p),
+        lib.or_quotient.argtypes = [ctypes.c_int32, i64p, i32p, u32p, i32p, u64p, i32p, P(i32p),
                                     P(ctypes.c_int64), P(i32p), P(i32p), P(u64p), P(ctypes.c_int64)]
         lib.or_free.argtypes = [ctypes.c_void_p]
         lib.or_diameter_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, u64p, u64p]
-        lib.or_sssp.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, u32p, u64p]
+        lib.or_sssp.argtypes = [ctypes.c_int32, i64p, i32p, u32p, ctypes.c_int32, u32p, u64p]
         _lib = lib
     return _lib
 
@@ -118,7 +118,9 @@ class Decomposition:
 
 
 def _csr_args(g):
-    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    """Row offsets as int64 (the oracle's offsets are 64-bit: graphs past 2^31
+    arcs), columns int32, weights uint32."""
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(g.col, dtype=np.int32)
     w = np.ascontiguousarray(g.w, dtype=np.uint32)
     return rp, col, w
@@ -145,7 +147,7 @@ def decompose(g, tau: int, seed: int, delta0: int = 0, log_cap: int = 256) -> De
     ld = np.zeros(log_cap, np.uint32)
     lg = _Log(_p(lu, ctypes.c_int32), _p(lc, ctypes.c_int32), _p(lv, ctypes.c_int32), _p(ld, ctypes.c_uint32),
               log_cap)
-    rc = _load().or_decompose(n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
+    rc = _load().or_decompose(n, _p(rp, ctypes.c_int64), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
                               tau, delta0, seed, _p(cluster, ctypes.c_int32), _p(D, ctypes.c_uint64),
                               ctypes.byref(st), ctypes.byref(lg))
     if rc != OR_OK:
@@ -177,7 +179,7 @@ def decompose_steps(g, tau: int, seed: int, delta0: int = 0, step_cap: int = 0,
     ld = np.zeros(log_cap, np.uint32)
     lg = _Log(_p(lu, ctypes.c_int32), _p(lc, ctypes.c_int32), _p(lv, ctypes.c_int32), _p(ld, ctypes.c_uint32),
               log_cap)
-    rc = _load().or_decompose_steps(n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
+    rc = _load().or_decompose_steps(n, _p(rp, ctypes.c_int64), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
                                     tau, delta0, seed, step_cap, _p(cluster, ctypes.c_int32),
                                     _p(D, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(ss), ctypes.byref(lg))
     if rc != OR_OK:
@@ -207,7 +209,7 @@ def decompose_cluster2(g, tau: int, seed: int, delta0: int = 0, log_cap: int = 2
     ld = np.zeros(log_cap, np.uint32)
     lg = _Log(_p(lu, ctypes.c_int32), _p(lc, ctypes.c_int32), _p(lv, ctypes.c_int32), _p(ld, ctypes.c_uint32),
               log_cap)
-    rc = _load().or_decompose_cluster2(n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32),
+    rc = _load().or_decompose_cluster2(n, _p(rp, ctypes.c_int64), _p(col, ctypes.c_int32),
                                        _p(w, ctypes.c_uint32), tau, delta0, seed, _p(cluster, ctypes.c_int32),
                                        _p(D, ctypes.c_uint64), ctypes.byref(st), ctypes.byref(r1),
                                        ctypes.byref(lg))
@@ -251,7 +253,7 @@ def quotient(g, dec: Decomposition) -> Quotient:
     ew = ctypes.POINTER(ctypes.c_uint64)()
     cl = np.ascontiguousarray(dec.cluster, dtype=np.int32)
     D = np.ascontiguousarray(dec.D, dtype=np.uint64)
-    rc = lib.or_quotient(g.n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
+    rc = lib.or_quotient(g.n, _p(rp, ctypes.c_int64), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32),
                          _p(cl, ctypes.c_int32), _p(D, ctypes.c_uint64), ctypes.byref(k), ctypes.byref(cen),
                          ctypes.byref(ne), ctypes.byref(ea), ctypes.byref(eb), ctypes.byref(ew), ctypes.byref(P))
     if rc != OR_OK:
@@ -300,7 +302,7 @@ def sssp(g, src: int):
     rp, col, w = _csr_args(g)
     dist = np.empty(g.n, dtype=np.uint32)
     mx = ctypes.c_uint64()
-    rc = _load().or_sssp(g.n, _p(rp, ctypes.c_int32), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32), src,
+    rc = _load().or_sssp(g.n, _p(rp, ctypes.c_int64), _p(col, ctypes.c_int32), _p(w, ctypes.c_uint32), src,
                          _p(dist, ctypes.c_uint32), ctypes.byref(mx))
     if rc != OR_OK:
         raise OracleError(rc, "or_sssp")

@@ -14,6 +14,9 @@
  *     baseline of Section 5 (exact distances, here by Dijkstra).
  * It shares no code with the GPU library.
  *
+ * Row offsets are 64-bit throughout, so the oracle also takes graphs of more
+ * than 2^31 arcs (one GPU's share of the billion-edge graphs of Section 5).
+ *
  * Readings taken where the paper is silent or ambiguous (each one is pinned
  * by a test against brute force or the mathematics):
  *   log is log2; gamma = 4 ln 2; the stage loop runs while
@@ -154,7 +157,7 @@ uint32_t or_default_delta(int64_t m, const uint32_t *w) {
   return d < 1 ? 1u : (uint32_t)(d > 0xffffffffu ? 0xffffffffu : d);
 }
 
-int or_decompose(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+int or_decompose(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *w,
                  uint32_t tau, uint32_t delta0, uint64_t seed,
                  int32_t *cluster, uint64_t *D, or_stats *st, or_stage_log *lg) {
   if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st) return OR_EINVAL;
@@ -204,7 +207,7 @@ int or_decompose(int32_t n, const int32_t *row_ptr, const int32_t *col, const ui
      * first relaxations into U are generated from U's side */
     for (int64_t i = 0; i < nU; ++i) {
       int32_t v = U[i];
-      for (int32_t a = row_ptr[v]; a < row_ptr[v + 1]; ++a) {
+      for (int64_t a = row_ptr[v]; a < row_ptr[v + 1]; ++a) {
         int32_t u = col[a];
         if (cluster[u] < 0) continue;
         if (heap_push(&h, w[a], (uint32_t)cluster[u], (uint32_t)v)) { rc = OR_ENOMEM; goto done; }
@@ -231,7 +234,7 @@ int or_decompose(int32_t n, const int32_t *row_ptr, const int32_t *col, const ui
         covered++;
         st->sum_acting++;
         st->sum_arcs += (uint64_t)(row_ptr[it.v + 1] - row_ptr[it.v]);
-        for (int32_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
+        for (int64_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
           int32_t x = col[a];
           if (cluster[x] >= 0 || settled[x] == s) continue;
           if (heap_push(&h, it.d + w[a], it.c, (uint32_t)x)) { rc = OR_ENOMEM; goto done; }
@@ -319,7 +322,7 @@ typedef struct {
   uint64_t updates;
 } or_step_stats;
 
-int or_decompose_steps(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+int or_decompose_steps(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *w,
                        uint32_t tau, uint32_t delta0, uint64_t seed, uint32_t step_cap,
                        int32_t *cluster, uint64_t *D, or_stats *st, or_step_stats *ss, or_stage_log *lg) {
   if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st || !ss) return OR_EINVAL;
@@ -394,7 +397,7 @@ int or_decompose_steps(int32_t n, const int32_t *row_ptr, const int32_t *col, co
           int32_t u = act[i];
           uint64_t du = dist[u];
           int heavy = 0;
-          for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+          for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
             uint64_t cand = du + w[a];
             if (cand > delta) { heavy = 1; continue; }
             ss->messages++;
@@ -433,7 +436,7 @@ int or_decompose_steps(int32_t n, const int32_t *row_ptr, const int32_t *col, co
         int reach = 0;
         for (int64_t i = 0; i < nblk && !reach; ++i) {
           int32_t u = blk[i];
-          for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
+          for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
             if (dist[col[a]] == UNSET) { reach = 1; break; }
         }
         if (!reach) break;
@@ -524,7 +527,7 @@ done:
  * iterations, levels = iterations, delta0 = the CLUSTER run's, delta_end =
  * Delta2, radius = max D; *radius1 = R_CL.
  */
-int or_decompose_cluster2(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+int or_decompose_cluster2(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *w,
                           uint32_t tau, uint32_t delta0, uint64_t seed,
                           int32_t *cluster, uint64_t *D, or_stats *st, uint64_t *radius1, or_stage_log *lg) {
   if (n < 1 || tau < 1 || !row_ptr || !cluster || !D || !st || !radius1) return OR_EINVAL;
@@ -569,7 +572,7 @@ int or_decompose_cluster2(int32_t n, const int32_t *row_ptr, const int32_t *col,
     /* Contract2's rescaled edges out of the clusters grown last iteration */
     for (int64_t k = 0; k < nprev; ++k) {
       int32_t u = prev[k];
-      for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+      for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
         int32_t v = col[a];
         if (cluster[v] >= 0 || w[a] > d2) continue;
         if (heap_push(&h, (uint64_t)loc[u] + w[a] - d2, (uint32_t)cluster[u], (uint32_t)v)) {
@@ -588,7 +591,7 @@ int or_decompose_cluster2(int32_t n, const int32_t *row_ptr, const int32_t *col,
       loc[it.v] = (uint32_t)it.d;
       lab[it.v] = it.c;
       cur[ncur++] = (int32_t)it.v;
-      for (int32_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
+      for (int64_t a = row_ptr[it.v]; a < row_ptr[it.v + 1]; ++a) {
         int32_t x = col[a];
         if (cluster[x] >= 0 || settled[x] == i) continue;
         if (it.d + w[a] > d2) continue;
@@ -649,7 +652,7 @@ static int cmp_qrec(const void *a, const void *b) {
  *   k, center[k]            cluster index -> center node id
  *   ne, ea[ne], eb[ne], ew[ne]  undirected edges a < b, sorted by (a, b)
  * Arrays are malloc'd here and freed with or_free. */
-int or_quotient(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+int or_quotient(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *w,
                 const int32_t *cluster, const uint64_t *D,
                 int32_t *k_out, int32_t **center_out, int64_t *ne_out,
                 int32_t **ea_out, int32_t **eb_out, uint64_t **ew_out, int64_t *pairs_out) {
@@ -660,7 +663,7 @@ int or_quotient(int32_t n, const int32_t *row_ptr, const int32_t *col, const uin
   int32_t *center = malloc((size_t)(k ? k : 1) * 4);
   int64_t P = 0;
   for (int32_t u = 0; u < n; ++u)
-    for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
+    for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a)
       if (u < col[a] && cluster[u] != cluster[col[a]]) P++;
   qrec_t *rec = malloc((size_t)(P ? P : 1) * sizeof(qrec_t));
   if (!center || !rec) { free(dense); free(center); free(rec); return OR_ENOMEM; }
@@ -668,7 +671,7 @@ int or_quotient(int32_t n, const int32_t *row_ptr, const int32_t *col, const uin
     if (dense[v] >= 0) center[dense[v]] = v;
   int64_t i = 0;
   for (int32_t u = 0; u < n; ++u)
-    for (int32_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
+    for (int64_t a = row_ptr[u]; a < row_ptr[u + 1]; ++a) {
       int32_t v = col[a];
       if (!(u < v) || cluster[u] == cluster[v]) continue;
       uint64_t x = (uint64_t)dense[cluster[u]], y = (uint64_t)dense[cluster[v]];
@@ -758,7 +761,7 @@ out:
 /* Single-source shortest paths on the input graph (the exact distances that
  * Delta-stepping computes).  dist is u32 with 0xFFFFFFFF for unreachable;
  * a finite distance that does not fit below that value is an overflow. */
-int or_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t src,
+int or_sssp(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t src,
             uint32_t *dist_out, uint64_t *max_out) {
   if (src < 0 || src >= n) return OR_EINVAL;
   int64_t m = row_ptr[n];
@@ -768,7 +771,7 @@ int or_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_
   heap_t h = {0};
   int rc = OR_OK;
   if (!rp || !ww || !dist) { rc = OR_ENOMEM; goto out; }
-  for (int32_t v = 0; v <= n; ++v) rp[v] = row_ptr[v];
+  memcpy(rp, row_ptr, ((size_t)n + 1) * 8);
   for (int64_t a = 0; a < m; ++a) ww[a] = w[a];
   if ((rc = dijkstra64(n, rp, col, ww, src, dist, &h))) goto out;
   uint64_t mx = 0;

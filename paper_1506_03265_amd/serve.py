@@ -99,11 +99,13 @@ def _run_one(req: Request, g, stream, keep: bool, driver: int) -> Result:
                   job.cluster[0] if keep else None, job.D[0] if keep else None)
 
 
-def serve(requests, graphs: dict, workers: int = 4, hbm_budget_bytes: int = 200 << 30, keep_outputs: bool = False,
+def serve(requests, graphs: dict, workers: int = 4, hbm_budget_bytes: int = 200 << 30, keep_outputs=False,
           driver: int = DRIVER_AUTO, time_scale: float = 1.0):
     """Runs the requests against resident graphs; returns (results sorted by
     request id, wall seconds).  Arrival times are honoured (scaled by
-    time_scale); latency is measured from each request's arrival."""
+    time_scale); latency is measured from each request's arrival.
+    keep_outputs: True keeps every request's cluster ids and distance bounds
+    on the device, a set of request ids keeps only those."""
     torch = _torch()
     reqs = sorted(requests, key=lambda r: r.arrival_s)
     budget = _Budget(hbm_budget_bytes)
@@ -120,7 +122,8 @@ def serve(requests, graphs: dict, workers: int = 4, hbm_budget_bytes: int = 200 
 
     def worker(slot: int, req: Request, nbytes: int):
         try:
-            r = _run_one(req, graphs[req.graph], streams[slot], keep_outputs, driver)
+            keep = keep_outputs if isinstance(keep_outputs, bool) else req.rid in keep_outputs
+            r = _run_one(req, graphs[req.graph], streams[slot], keep, driver)
             r.arrival_s += t_start
             with lock:
                 results.append(r)

@@ -2,8 +2,9 @@
 16.8M nodes, 64.1M arcs; R-MAT scale 24, 8.9M nodes, 521M arcs; tau = 4,
 seed 1), in the launch configuration the benchmark times.  Expected values were written by the oracle
 (tests/golden/make_workload_counts.py): per-node outputs are compared through
-SHA-256 digests of the oracle's arrays, plus stage counts, the quotient size
-and the estimate."""
+SHA-256 digests of the oracle's arrays, plus stage counts, the quotient graph
+(digests of its centers and of its symmetric CSR: row offsets, columns,
+weights), the estimate, and the Delta-stepping competitor's distances."""
 import hashlib
 import json
 import os
@@ -21,6 +22,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _check_quotient(q, ref):
+    """The quotient graph equals the oracle's: k, arc count and the digests of
+    its centers (int32), row offsets (int64), columns (int32), weights (u64)."""
+    assert q.k == ref["quotient_k"] and q.qm == 2 * ref["quotient_edges"]
+    got = dict(center=_digest(q.center.cpu().numpy()), row_ptr=_digest(q.row_ptr.cpu().numpy()),
+               col=_digest(q.col.cpu().numpy()), w=_digest(cd.u64(q.w)))
+    assert got == ref["quotient_sha256"]
 
 
 @pytest.fixture(scope="module")
@@ -51,9 +61,22 @@ def test_road4096_decompose_quotient_estimate(road, driver):
     assert _digest(cluster.cpu().numpy()) == counts["cluster_sha256"]
     assert _digest(cd.u64(D)) == counts["D_sha256"]
     q = cd.cldiam_build_quotient(dg, cluster, D)
-    assert q.k == counts["quotient_k"] and q.qm == 2 * counts["quotient_edges"]
+    _check_quotient(q, counts)
     phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
     assert (phi, approx) == (counts["phi_gc"], counts["phi_approx"])
+
+
+def test_road4096_sssp_equals_dijkstra(road):
+    """The competitor's Delta-stepping distances from the source rule, with
+    the default bucket width and with the benchmark's best, against the
+    oracle's Dijkstra (digest of all 16.8M distances)."""
+    g, counts, dg = road
+    ref = counts["sssp"]
+    for bd in (0, 16 * 5000):
+        print(f"[fullsize] sssp src={ref['source']} bucket={bd}", file=sys.stderr, flush=True)
+        dist, mx = cd.cldiam_sssp_delta_stepping(dg, ref["source"], bd)
+        assert mx == ref["max_dist"]
+        assert _digest(cd.u32(dist)) == ref["dist_sha256"]
 
 
 def test_road4096_invariants_on_samples(road):
@@ -88,7 +111,7 @@ def test_road4096_variants(road, variant):
     assert _digest(cluster.cpu().numpy()) == ref["cluster_sha256"]
     assert _digest(cd.u64(D)) == ref["D_sha256"]
     q = cd.cldiam_build_quotient(dg, cluster, D)
-    assert q.k == ref["quotient_k"]
+    _check_quotient(q, ref)
     phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
     assert (phi, approx) == (ref["phi_gc"], ref["phi_approx"])
 
@@ -138,6 +161,6 @@ def test_rmat24_decompose_quotient_estimate():
     assert _digest(cd.u64(D)) == counts["D_sha256"]
     print("[fullsize] rmat24 quotient", file=sys.stderr, flush=True)
     q = cd.cldiam_build_quotient(dg, cluster, D)
-    assert q.k == counts["quotient_k"] and q.qm == 2 * counts["quotient_edges"]
+    _check_quotient(q, counts)
     phi, approx = cd.cldiam_estimate_diameter(q, st.radius)
     assert (phi, approx) == (counts["phi_gc"], counts["phi_approx"])
