@@ -93,6 +93,7 @@ def test_serve2000_mix_equals_plain_and_oracle():
     _say(f"[configs] generating {len(keys)} resident graphs")
     pool = {}
     for k in keys:
+        _say(f"[configs] resident graph {k}")
         if k.startswith("grid"):
             s = int(k[4:])
             g = graphgen.grid(s, s, 10000, s)
