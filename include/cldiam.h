@@ -293,6 +293,22 @@ int cldiam_estimate_diameter(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, c
                              const uint64_t *d_qw, uint64_t radius, uint64_t *h_phi_gc, uint64_t *h_phi_approx,
                              void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same estimate
+ * with no workspace argument.  Its scratch (control words and, above 3072
+ * quotient nodes, per-workgroup distance and queue slices) is a static 32 MiB
+ * device array of the library; each GPU holds its own copy from the first
+ * call on that device until the process ends.  The call allocates nothing
+ * (no device or pinned memory; results are read back into host stack memory).
+ * k above CLDIAM_NOALLOC_MAX_K returns CLDIAM_EINVAL before any device work.
+ * Every call on one GPU uses that GPU's array: calls that overlap in time on
+ * the same GPU (from several threads or streams) race and must not be made.
+ * Results are identical to cldiam_estimate_diameter's. */
+#define CLDIAM_NOALLOC_MAX_K 32768
+int cldiam_estimate_diameter_noalloc(int32_t k, int64_t qm, const int64_t *d_qrow_ptr, const int32_t *d_qcol,
+                                     const uint64_t *d_qw, uint64_t radius, uint64_t *h_phi_gc,
+                                     uint64_t *h_phi_approx, void *stream);
+
 /* ------------------------------------------------ SSSP (the competitor) ---
  * Delta-stepping single-source shortest paths (Meyer and Sanders), the
  * baseline of Section 5: twice the largest finite distance from one source is

@@ -25,6 +25,7 @@ CLDIAM_EOVERFLOW = -3
 CLDIAM_EHIP = -4
 CLDIAM_ESTAGES = -5
 CLDIAM_ETIMEOUT = -6
+CLDIAM_NOALLOC_MAX_K = 32768   # largest quotient of cldiam_estimate_diameter_noalloc
 STAGE_LOG = 64
 
 DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
@@ -35,7 +36,7 @@ EXPORTS = [
     "cldiam_load_csr_workspace_size", "cldiam_load_csr",
     "cldiam_decompose_workspace_size", "cldiam_decompose_batch", "cldiam_decompose",
     "cldiam_quotient_workspace_size", "cldiam_build_quotient",
-    "cldiam_estimate_workspace_size", "cldiam_estimate_diameter",
+    "cldiam_estimate_workspace_size", "cldiam_estimate_diameter", "cldiam_estimate_diameter_noalloc",
     "cldiam_sssp_workspace_size", "cldiam_sssp_delta_stepping",
     "cldiam_server_workspace_size", "cldiam_server_create", "cldiam_server_destroy", "cldiam_server_submit",
     "cldiam_server_step", "cldiam_server_poll",
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.cldiam_build_quotient.argtypes = [I32, I64, V, V, V, V, V, V, V, V, P(I32), P(I64), V, SZ, V]
     lib.cldiam_estimate_workspace_size.argtypes, lib.cldiam_estimate_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_estimate_diameter.argtypes = [I32, I64, V, V, V, U64, P(U64), P(U64), V, SZ, V]
+    lib.cldiam_estimate_diameter_noalloc.argtypes = [I32, I64, V, V, V, U64, P(U64), P(U64), V]
     lib.cldiam_sssp_workspace_size.argtypes, lib.cldiam_sssp_workspace_size.restype = [I32, I64], SZ
     lib.cldiam_sssp_delta_stepping.argtypes = [I32, I64, V, V, I32, U32, V, P(U64), V, SZ, V]
     lib.cldiam_server_workspace_size.argtypes, lib.cldiam_server_workspace_size.restype = [I64, I32], SZ
@@ -116,7 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.cldiam_server_step.argtypes = [V, I32, P(I32), P(I32)]
     lib.cldiam_server_poll.argtypes = [V, P(U64), P(_Stats), I32, P(I32)]
     for name in ("cldiam_load_csr", "cldiam_decompose_batch", "cldiam_decompose", "cldiam_build_quotient",
-                 "cldiam_estimate_diameter", "cldiam_sssp_delta_stepping", "cldiam_server_create",
+                 "cldiam_estimate_diameter", "cldiam_estimate_diameter_noalloc", "cldiam_sssp_delta_stepping",
+                 "cldiam_server_create",
                  "cldiam_server_submit", "cldiam_server_step", "cldiam_server_poll"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

@@ -69,6 +69,16 @@ def test_sssp_accepts_the_default_width_marker(lib):
     assert b"bucket" not in lib.cldiam_last_error()
 
 
+def test_noalloc_estimate_rejects_k_above_its_maximum_before_device_work(lib):
+    import ctypes
+    phi, approx = ctypes.c_uint64(), ctypes.c_uint64()
+    fake = ctypes.c_void_p(256)   # never dereferenced: the size check comes first
+    rc = lib.cldiam_estimate_diameter_noalloc(cd.CLDIAM_NOALLOC_MAX_K + 1, 0, fake, None, None, 0,
+                                              ctypes.byref(phi), ctypes.byref(approx), None)
+    assert rc == cd.CLDIAM_EINVAL
+    assert b"maximum" in lib.cldiam_last_error()
+
+
 def test_pinned_host_bytes_is_a_pool_of_whole_buffers(lib):
     b = lib.cldiam_pinned_host_bytes()
     assert b >= 0 and b % 4096 == 0
