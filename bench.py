@@ -411,7 +411,11 @@ def variants_bench(args):
 def delta0_bench(args):
     """Initial-Delta experiment (Section 5): a 2048 x 2048 mesh whose edges
     weigh 10^6 with probability 0.1 and 1 otherwise; CL-DIAM started from the
-    minimum weight, from the mean weight and from about the diameter."""
+    minimum weight, from the mean weight and from about the diameter, under
+    both the fixpoint growth (the default) and the literal step-synchronous
+    PartialGrowth.  Only the literal form stops a growth after the step that
+    covers half of the nodes, whatever the distances reached by then, so
+    only it can show the paper's loss of quality for a large initial Delta."""
     import graphgen
     import oracle
     import paper_1506_03265_amd as cd
@@ -422,20 +426,28 @@ def delta0_bench(args):
     lb = _sssp_lower_bound(cd, dg, oracle.sssp_source(g.n, 1))
     mean = int(dg.weight_sum // max(g.m, 1))
     rows = []
-    for label, d0 in (("min weight", 1), ("mean weight", mean), ("~diameter", lb)):
-        st, est, t, td = _pipeline(cd, dg, args.tau, 1, delta0=d0, reps=args.steps)
-        rows.append({"delta0": label, "value": d0, "ms": round(t * 1e3, 3), "levels": st.levels,
-                     "sweeps": st.sweeps, "stages": st.stages, "delta_end": st.delta_end,
-                     "clusters": st.num_clusters, "radius": st.radius, "phi_approx": est[1],
-                     "ratio_to_lower_bound": round(est[1] / lb, 4)})
-        log(f"[bench] delta0 {label}: {rows[-1]}")
+    for vname, var in (("fixpoint", cd.VARIANT_FIXPOINT), ("steps", cd.VARIANT_STEPS)):
+        for label, d0 in (("min weight", 1), ("mean weight", mean), ("~diameter", lb)):
+            st, est, t, td = _pipeline(cd, dg, args.tau, 1, delta0=d0, variant=var, reps=args.steps)
+            rows.append({"variant": vname, "delta0": label, "value": d0, "ms": round(t * 1e3, 3),
+                         "levels": st.levels, "sweeps": st.sweeps, "stages": st.stages, "delta_end": st.delta_end,
+                         "clusters": st.num_clusters, "radius": st.radius, "phi_approx": est[1],
+                         "ratio_to_lower_bound": round(est[1] / lb, 4)})
+            if var == cd.VARIANT_STEPS:
+                rows[-1].update(rounds=st.rounds, messages=st.messages, updates=st.updates)
+            log(f"[bench] {vname} delta0 {label}: {rows[-1]}")
+    by = {(r["variant"], r["delta0"]): r for r in rows}
     return {
         "metric": "initial-Delta experiment: approximation ratio to an SSSP lower bound and time per initial Delta",
-        "value": rows[1]["ratio_to_lower_bound"], "unit": "ratio", "n_gpus": 1, "steps": args.steps, "warmup": 0,
-        "ms_per_step": rows[1]["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"{side}x{side} mesh, weights 10^6 w.p. 0.1 else 1, graph seed 1, tau={args.tau}",
-                   "n": g.n, "m_arcs": g.m, "sssp_lower_bound": lb, "runs": rows},
+        "value": by[("steps", "~diameter")]["ratio_to_lower_bound"], "unit": "ratio", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0, "ms_per_step": by[("steps", "~diameter")]["ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{side}x{side} mesh, weights 10^6 w.p. 0.1 else 1, graph seed 1, tau={args.tau}; "
+                               "value = literal step-synchronous variant started at about the diameter",
+                   "n": g.n, "m_arcs": g.m, "sssp_lower_bound": lb,
+                   "paper": "Section 5 reports about 2.5x for an initial Delta equal to the diameter against "
+                            "1.0001 for the minimum weight (Spark, real weights)",
+                   "runs": rows},
     }
 
 
