@@ -90,7 +90,10 @@ def step_bench(args, name):
 
     job = cd.DecomposeJob([dg], [(counts["tau"], counts["seed"], 0)], driver=args.driver,
                           local_rounds=args.local_rounds, grid_blocks=args.grid_blocks,
-                          bucket_width=args.bucket_width, row_bucket_shift=args.row_shift)
+                          bucket_width=args.bucket_width, row_bucket_shift=args.row_shift,
+                          chunk_factor=args.chunk_factor, wave_row_min=args.wave_row_min,
+                          group_row_min=args.group_row_min, local_queue=args.local_queue,
+                          local_cutoff=args.local_cutoff)
     qjob = cd.QuotientJob(dg)
     ejob = cd.EstimateJob(1, 1, dev)   # grows to the quotient's size on first use
 
@@ -699,6 +702,13 @@ def main():
                     help="long-row bucket: Delta / 2^shift (0 = library default, < 0 = none)")
     ap.add_argument("--bucket-width", type=float, default=0.0,
                     help="relaxation distance bucket in mean arc weights (0 default, < 0 none)")
+    ap.add_argument("--chunk-factor", type=int, default=0, help="growth chunks per workgroup (0 = default)")
+    ap.add_argument("--wave-row-min", type=int, default=0, help="rows above this many arcs go to a wave (0 = default)")
+    ap.add_argument("--group-row-min", type=int, default=0,
+                    help="rows above this many arcs go to the workgroup (0 = default)")
+    ap.add_argument("--local-queue", type=int, default=0, help="local queue tile (0 = default)")
+    ap.add_argument("--local-cutoff", type=int, default=0,
+                    help="percentage of finished workgroups that ends local rounds (0 = default)")
     ap.add_argument("--decompose-only", action="store_true", help="time only the decomposition (for profiles)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer three times (reference kernel for HBM counters)")

@@ -184,9 +184,9 @@ typedef struct {
 /* Schedule knobs of a decomposition job.  They change only how the work is
  * scheduled on the device, never the results. */
 typedef struct {
-  int32_t local_rounds; /* workgroup-local relaxation rounds per sweep (16 while a frontier has at most
-                           32768 nodes); < 0 = default: 8 on graphs with at most 16 arcs per node,
-                           on denser ones 2 above 2^21 nodes and 0 below */
+  int32_t local_rounds; /* workgroup-local relaxation rounds per sweep (at least 16 while a frontier has
+                           at most 32768 nodes); < 0 = default: 16 on graphs with at most 16 arcs per
+                           node, on denser ones 2 above 2^21 nodes and 0 below */
   int32_t grid_blocks;  /* workgroups per sweep; 0 = one per compute unit */
   float bucket_width;   /* distance bucket of a relaxation sweep, in mean arc weights: a sweep relaxes
                            only frontier nodes whose tentative distance is below (smallest distance on
@@ -201,6 +201,18 @@ typedef struct {
   int32_t chunk_factor; /* chunks of a growth sweep per workgroup: the first goes to each workgroup, the
                            rest to whichever workgroup is free next; 0 = default (3 on graphs of more
                            than 2^21 nodes with more than 16 arcs per node, else 1), at most 64 */
+  int32_t wave_row_min; /* threads per row: rows of more arcs than this are relaxed by one wave (64
+                           threads) instead of one thread, and take the long-row bucket above;
+                           0 = default (32; 128 on graphs with more than 16 arcs per node), at most
+                           2^20 */
+  int32_t group_row_min;/* rows of more arcs than this are relaxed by the whole workgroup (1024 threads);
+                           0 = default (8192), at least wave_row_min */
+  int32_t local_queue;  /* queue tile of the local rounds: slots of a workgroup's queue of improved nodes
+                           (64 .. 4096); 0 = default (4096) */
+  int32_t local_cutoff; /* a workgroup ends its local rounds once this percentage of the sweep's
+                           workgroups have finished the sweep (their work then waits for the next sweep,
+                           which spreads it over the whole grid); 1 .. 100 (100: never), 0 = default
+                           (75) */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
 

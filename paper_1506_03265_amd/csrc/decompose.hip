@@ -108,6 +108,9 @@ struct GDesc {
   int32_t local_rounds;  // workgroup-local relaxation rounds per RELAX run
   int32_t row_shift;     // long rows use a bucket of width Delta >> row_shift; < 0 = none
   int32_t chunk_factor;  // RELAX / NEXT chunks per workgroup and sweep
+  int32_t mid_deg;       // rows of more arcs are relaxed by one wave ("long rows")
+  int32_t big_deg;       // rows of more arcs are relaxed by the whole workgroup
+  uint32_t lq_cap;       // slots of the local relaxation queue used (at most kLocalCap)
 };
 
 // Control-owned state of one graph.
@@ -161,6 +164,7 @@ struct Ctl {
   unsigned long long t_limit;   // ticks after which the job stops with a timeout
   PadU64 arcs;                  // arcs read by relaxation (diagnostic)
   PadU32 cursor;                // chunks of the current sweep taken beyond the first nblocks
+  PadU32 idle;                  // workgroups that have finished the current sweep
   CldBarrier bar;
 };
 
@@ -174,7 +178,7 @@ struct Job {
   int32_t *log;      // G x CLDIAM_STAGE_LOG x 4
   uint64_t *key;
   uint64_t *keyn;    // synchronous steps: state after the current step (key holds the state before it);
-                     // otherwise, for rows above kMidDeg arcs, the key of the row's last scan
+                     // otherwise, for long rows, the key of the row's last scan
   uint32_t *slim;    // with keyn: the light limit (Delta - d) of that scan; arcs up to it have been offered
   uint64_t *R;
   uint32_t *fstamp;
@@ -184,16 +188,22 @@ struct Job {
   int32_t *C;
   int32_t G;
   int32_t nblocks;        // workgroups of a sweep launch
+  uint32_t cutoff;        // a workgroup ends its local rounds once this many workgroups have finished the
+                          // sweep (the rounds are optional: every improved node is on the next frontier)
 };
 
-constexpr int kThreads = 1024;
-constexpr int kStageCap = 4096;   // LDS staging slots per output list
-constexpr int kLocalCap = 4096;   // LDS local-round queue slots
-constexpr int kMidDeg = 32;       // rows above this degree are relaxed by one wave
-constexpr int kBigDeg = 8192;     // rows above this degree are relaxed by the whole workgroup
-constexpr int kMidCap = 2048;     // deferred wave rows per round
-constexpr int kBigCap = 128;      // deferred workgroup rows per round
-constexpr int kLocalRounds = 8;   // default local relaxation rounds per RELAX run
+constexpr int kThreads = 1024;        // control workgroup
+constexpr int kSweepThreads = 1024;   // sweep workgroup
+constexpr int kCuThreads = 1024;      // sweep threads resident per CU (16 waves at the sweep's register use)
+constexpr int kStageCap = 4 * kSweepThreads;   // LDS staging slots per output list
+constexpr int kLocalCap = 4 * kSweepThreads;   // LDS local-round queue slots
+constexpr int kMidDeg = 32;       // default: rows above this degree are relaxed by one wave
+constexpr int kBigDeg = 8192;     // default: rows above this degree are relaxed by the whole workgroup
+constexpr int kMidCap = 2 * kSweepThreads;   // deferred wave rows per round
+constexpr int kBigCap = kSweepThreads / 8;   // deferred workgroup rows per round
+constexpr int kLocalRounds = 16;  // default local relaxation rounds per RELAX run
+constexpr int kLocalCutoffPct = 75;    // default: local rounds end once this % of workgroups finished the sweep
+constexpr int kDenseWaveRow = 128;     // default wave_row_min on graphs of more than kDenseDegree arcs per node
 constexpr int kLocalRoundsDense = 2;   // ... on graphs with more than kDenseDegree arcs per node and
 constexpr int kDenseDegree = 16;       // more than kDenseLarge nodes (none on smaller dense graphs)
 constexpr int32_t kDenseLarge = 1 << 21;
@@ -203,7 +213,7 @@ constexpr int32_t kRowShiftMax = 8;
 constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get kSmallRounds local rounds
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
-constexpr uint32_t kPassChunk = kThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
+constexpr uint32_t kPassChunk = kSweepThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
 
 // ------------------------------------------------------------- control --
 
@@ -249,7 +259,7 @@ __device__ __forceinline__ uint32_t bucket_limit(const GDesc &d, uint32_t lo) {
   return t < 0xffffffffull ? (uint32_t)t : 0xffffffffu;
 }
 
-// Upper end (exclusive) of the narrower bucket of rows of more than kMidDeg
+// Upper end (exclusive) of the narrower bucket of rows of more than mid_deg
 // arcs.  Relaxing such a row before its node's distance is nearly final
 // costs a full rescan when the distance drops again, so these rows wait
 // until the frontier minimum comes within Delta / 2^row_shift of them.
@@ -545,6 +555,7 @@ __device__ void control_block(const Job &job) {
     job.seg[job.G] = carry;
     ctl->total = carry;
     ctl->cursor.v = 0;
+    ctl->idle.v = 0;
     ctl->sweep_id = sweep_id;
     ctl->iterations++;
     ctl->done = alldone;
@@ -553,6 +564,11 @@ __device__ void control_block(const Job &job) {
 }
 
 // --------------------------------------------------------------- sweeps --
+
+struct Out {
+  int32_t *list;     // list base for this graph (offset applied)
+  uint32_t *count;   // its global counter
+};
 
 // LDS staging of up to three output lists of one graph run.
 struct Stage {
@@ -574,11 +590,8 @@ struct Stage {
   uint32_t flush;           // a list passed the flush threshold
   uint32_t fmin;            // RELAX: smallest distance pushed on the next frontier
   uint32_t chunk;           // next chunk of this workgroup
-};
-
-struct Out {
-  int32_t *list;     // list base for this graph (offset applied)
-  uint32_t *count;   // its global counter
+  uint32_t stop;            // local rounds end early: most of the grid has finished the sweep
+  Out out[3];               // output lists of the current run (in LDS: the flush indexes them by list number)
 };
 
 // Stage v on output list k; falls back to a direct global slot when the LDS
@@ -598,13 +611,22 @@ __device__ void stage_flush(Stage &S, const Out *out, int nout) {
   if (threadIdx.x < (unsigned)nout) {
     const int k = threadIdx.x;
     const uint32_t n = S.cnt[k] < kStageCap ? S.cnt[k] : kStageCap;
-    S.base[k] = n ? atomicAdd(out[k].count, n) : 0;
+    uint32_t *count = k == 0 ? out[0].count : (k == 1 ? out[1].count : out[2].count);
+    S.base[k] = n ? atomicAdd(count, n) : 0;
     S.cnt[k] = n;
   }
   __syncthreads();
-  for (int k = 0; k < nout; ++k) {
-    const uint32_t n = S.cnt[k], b = S.base[k];
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[k].list[b + i] = S.buf[k][i];
+  {
+    const uint32_t n = S.cnt[0], b = S.base[0];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[0].list[b + i] = S.buf[0][i];
+  }
+  if (nout > 1) {
+    const uint32_t n = S.cnt[1], b = S.base[1];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[1].list[b + i] = S.buf[1][i];
+  }
+  if (nout > 2) {
+    const uint32_t n = S.cnt[2], b = S.base[2];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[2].list[b + i] = S.buf[2][i];
   }
   __syncthreads();
   if (threadIdx.x < 3) S.cnt[threadIdx.x] = 0;
@@ -632,8 +654,8 @@ constexpr int kArcBatch = 4;
 
 // Queues a long row for the cooperative passes of this round; false when the
 // queue is full (the caller then handles the row itself).
-__device__ __forceinline__ bool defer_row(Stage &S, int32_t u, int32_t deg) {
-  if (deg > kBigDeg) {
+__device__ __forceinline__ bool defer_row(Stage &S, int32_t u, int32_t deg, int32_t big_deg) {
+  if (deg > big_deg) {
     const uint32_t slot = atomicAdd(&S.big_cnt, 1u);
     if (slot < kBigCap) { S.big[slot] = u; return true; }
   } else {
@@ -643,9 +665,9 @@ __device__ __forceinline__ bool defer_row(Stage &S, int32_t u, int32_t deg) {
   return false;
 }
 
-__device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v) {
+__device__ __forceinline__ void lq_push(uint32_t *lq_cnt, int32_t *lq, int32_t v, uint32_t cap) {
   const uint32_t slot = atomicAdd(lq_cnt, 1u);
-  if (slot < kLocalCap) lq[slot] = v;
+  if (slot < cap) lq[slot] = v;
 }
 
 __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta,
@@ -659,7 +681,7 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
   if (!later) {
     a0 = d.row_ptr[u];
     deg = (int32_t)(d.row_ptr[u + 1] - a0);
-    later = deg > kMidDeg && (uint32_t)(ku >> 32) >= theta_row;
+    later = deg > d.mid_deg && (uint32_t)(ku >> 32) >= theta_row;
   }
   if (later) {
     // beyond the current distance bucket: stays on the frontier for a later
@@ -670,7 +692,7 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
     }
     return 0;
   }
-  if (deg > kMidDeg && defer_row(S, u, deg)) return 0;
+  if (deg > d.mid_deg && defer_row(S, u, deg, d.big_deg)) return 0;
   const uint64_t *row = d.arcs + a0;
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
   bool blocked = false;
@@ -713,7 +735,7 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
       }
       if (!ok[j]) continue;
       if (cur[j] == CLD_INF64) stage_push(S, out, 1, v);
-      if (lq) lq_push(lq_cnt, lq, v);
+      if (lq) lq_push(lq_cnt, lq, v, d.lq_cap);
     }
   }
   if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
@@ -726,7 +748,7 @@ __device__ __forceinline__ uint32_t relax_sync(const Job &job, const GDesc &d, i
                                                const Out *out) {
   const int64_t a0 = d.row_ptr[u];
   const int32_t deg = (int32_t)(d.row_ptr[u + 1] - a0);
-  if (deg > kMidDeg && defer_row(S, u, deg)) return 0;
+  if (deg > d.mid_deg && defer_row(S, u, deg, d.big_deg)) return 0;
   const uint64_t *row = d.arcs + a0;
   const uint64_t ku = job.key[off + u];
   const uint32_t lim = delta - (uint32_t)(ku >> 32);
@@ -768,7 +790,7 @@ __device__ __forceinline__ uint32_t relax_sync(const Job &job, const GDesc &d, i
 
 // One arc of a cooperative row: the same offer as in relax_item.
 __device__ __forceinline__ void relax_one(const Job &job, int64_t off, uint64_t ku, uint64_t arc, uint32_t it,
-                                          Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq) {
+                                          Stage &S, const Out *out, uint32_t *lq_cnt, int32_t *lq, uint32_t lq_cap) {
   const int32_t v = (int32_t)(uint32_t)arc;
   const int64_t gv = off + v;
   const uint64_t cand = ku + (arc & 0xffffffff00000000ull);
@@ -780,7 +802,7 @@ __device__ __forceinline__ void relax_one(const Job &job, int64_t off, uint64_t 
     }
     if (cand < old) {
       if (old == CLD_INF64) stage_push(S, out, 1, v);
-      if (lq) lq_push(lq_cnt, lq, v);
+      if (lq) lq_push(lq_cnt, lq, v, lq_cap);
     }
   }
 }
@@ -905,7 +927,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
         if (light) {
           ++scanned;
           if (mode == 2) relax_one_sync(job, off, ku, arc, it, S, out);
-          else relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq);
+          else relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq, d.lq_cap);
         }
       }
       if (lane == 0 && (uint32_t)(row[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
@@ -955,14 +977,14 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
       for (int32_t a = start + (int32_t)threadIdx.x; a < lo; a += (int32_t)blockDim.x) {
         ++scanned;
         if (mode == 2) relax_one_sync(job, off, ku, row[a], it, S, out);
-        else relax_one(job, off, ku, row[a], it, S, out, lq_cnt, lq);
+        else relax_one(job, off, ku, row[a], it, S, out, lq_cnt, lq, d.lq_cap);
       }
       if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
       // keep LDS staging within bounds between rows
       __syncthreads();
       // every thread's part of the row is done: record the scan
       if (resume && threadIdx.x == 0) note_scan(job, off, u, ku, lim);
-      if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      if (threadIdx.x < 3 && S.cnt[threadIdx.x] > kStageCap - kSweepThreads) S.flush = 1;
       __syncthreads();
       if (S.flush) stage_flush(S, out, 3);
     } else {
@@ -1038,32 +1060,32 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   const uint32_t theta_row = row_lim < theta ? row_lim : theta;
   const uint32_t fcur = s.fcur, fnxt = s.fnxt, blk = s.blk;
   const uint64_t T = s.T;
-  Out out[3];
+  Out o[3] = {};
   int nout = 0;
   switch (phase) {
     case PH_SELECT:
-      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
-      out[1] = {job.C + off, &cn.cntC.v};
+      o[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      o[1] = {job.C + off, &cn.cntC.v};
       nout = 2;
       break;
     case PH_RELAX:
-      out[0] = {job.pool[fnxt] + off, &cn.cnt[fnxt].v};
-      out[1] = {job.C + off, &cn.cntC.v};
-      out[2] = {job.pool[blk] + off, &cn.cnt[blk].v};
+      o[0] = {job.pool[fnxt] + off, &cn.cnt[fnxt].v};
+      o[1] = {job.C + off, &cn.cntC.v};
+      o[2] = {job.pool[blk] + off, &cn.cnt[blk].v};
       nout = 3;
       break;
     case PH_COMPACT:
-      out[0] = {job.U[ucur ^ 1] + off, &cn.cntU[ucur ^ 1].v};
+      o[0] = {job.U[ucur ^ 1] + off, &cn.cntU[ucur ^ 1].v};
       nout = 1;
       break;
     case PH_MERGE:
-      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      o[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
       nout = 1;
       break;
     case PH_C2_SELECT:
     case PH_C2_BOUNDARY:
-      out[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
-      out[1] = {job.C + off, &cn.cntC.v};
+      o[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
+      o[1] = {job.C + off, &cn.cntC.v};
       nout = 2;
       break;
     default:
@@ -1072,6 +1094,9 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   const bool steps = d.variant == CLDIAM_VARIANT_STEPS;
   const bool resume = !steps && !s.c2;   // long rows resume their last scan (keyn/slim hold scan records)
   if (threadIdx.x == 0) {
+    S.out[0] = o[0];
+    S.out[1] = o[1];
+    S.out[2] = o[2];
     S.acc = (phase == PH_NEXT) ? CLD_INF64 : 0ull;
     S.acc32 = 0;
     S.fmin = 0xffffffffu;
@@ -1081,6 +1106,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.big_cnt = 0;
   }
   __syncthreads();
+  const Out *out = S.out;
   uint32_t scanned = 0;
   for (uint32_t r = a; r < b; r += blockDim.x) {
     const uint32_t i = r + threadIdx.x;
@@ -1153,7 +1179,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
         case PH_NEXT: {
           const int32_t u = job.pool[blk][off + idx];
           const int32_t deg = (int32_t)(d.row_ptr[u + 1] - d.row_ptr[u]);
-          if (deg > kMidDeg && defer_row(S, u, deg)) break;
+          if (deg > d.mid_deg && defer_row(S, u, deg, d.big_deg)) break;
           const uint64_t best = next_small(job, d, off, delta, u);
           if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
           break;
@@ -1204,7 +1230,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
                            steps ? nullptr : S.lq[0], phase == PH_NEXT ? 1 : (steps ? 2 : 0), resume);
     if (nout) {
       __syncthreads();
-      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kSweepThreads) S.flush = 1;
       __syncthreads();
       if (S.flush) stage_flush(S, out, nout);
     }
@@ -1221,9 +1247,12 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     const int rounds = (d.local_rounds > 0 && graph_items <= kSmallFrontier && d.local_rounds < kSmallRounds)
                            ? kSmallRounds : d.local_rounds;
     for (int round = 0; round < rounds; ++round) {
+      if (threadIdx.x == 0)
+        S.stop = job.cutoff < (uint32_t)job.nblocks &&
+                 __hip_atomic_load(&job.ctl->idle.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= job.cutoff;
       __syncthreads();
-      const uint32_t n = S.lq_cnt[q] < kLocalCap ? S.lq_cnt[q] : kLocalCap;
-      if (n == 0) break;
+      const uint32_t n = S.lq_cnt[q] < d.lq_cap ? S.lq_cnt[q] : d.lq_cap;
+      if (n == 0 || S.stop) break;
       if (threadIdx.x == 0) S.lq_cnt[q ^ 1] = 0;
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
@@ -1231,7 +1260,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
                               &S.lq_cnt[q ^ 1], S.lq[q ^ 1]);
       scanned += coop_rows(job, d, off, delta, it, level_id, S, out, &S.lq_cnt[q ^ 1], S.lq[q ^ 1], 0, resume);
       __syncthreads();
-      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kThreads) S.flush = 1;
+      if (threadIdx.x < (unsigned)nout && S.cnt[threadIdx.x] > kStageCap - kSweepThreads) S.flush = 1;
       __syncthreads();
       if (S.flush) stage_flush(S, out, nout);
       q ^= 1;
@@ -1285,6 +1314,7 @@ __device__ void sweep(const Job &job, uint32_t block, uint32_t nblocks, Stage &S
     v = S.chunk;
     __syncthreads();
   }
+  if (threadIdx.x == 0) atomicAdd(&job.ctl->idle.v, 1u);
   for (int o = 32; o >= 1; o >>= 1) scanned += __shfl_xor(scanned, o);
   if (cld_lane() == 0 && scanned) atomicAdd(&job.ctl->arcs.v, (unsigned long long)scanned);
 }
@@ -1312,6 +1342,7 @@ __global__ void __launch_bounds__(256) k_init(Job job, int64_t total_n) {
 // Fresh state for one graph of a server job (node range [off, off + n)).
 __global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     job.key[off + i] = CLD_INF64;
     job.keyn[off + i] = CLD_INF64;
@@ -1325,13 +1356,13 @@ __global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_
 
 __global__ void __launch_bounds__(kThreads) k_control(Job job) { control_block(job); }
 
-__global__ void __launch_bounds__(kThreads) k_sweep(Job job) {
+__global__ void __launch_bounds__(kSweepThreads) k_sweep(Job job) {
   __shared__ Stage S;
   if (job.ctl->done) return;
   sweep(job, blockIdx.x, gridDim.x, S);
 }
 
-__global__ void __launch_bounds__(kThreads) k_persistent(Job job) {
+__global__ void __launch_bounds__(kSweepThreads) k_persistent(Job job) {
   __shared__ Stage S;
   const uint32_t nb = gridDim.x;
   for (;;) {
@@ -1406,12 +1437,13 @@ static_assert(sizeof(Ctl) <= cld::kPinnedBytes, "control block must fit a pooled
 // co-resident maximum for the persistent kernel).
 int grid_blocks(int driver, int requested, int *blocks) {
   int coop_blocks = 0;
-  int rc = cld::cooperative_blocks((const void *)k_persistent, kThreads, 1, &coop_blocks);
+  int rc = cld::cooperative_blocks((const void *)k_persistent, kSweepThreads, kCuThreads / kSweepThreads,
+                                   &coop_blocks);
   if (rc) return rc;
   int dev = 0, cus = 0;
   CLD_HIP(hipGetDevice(&dev));
   CLD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int want = requested > 0 ? requested : cus;
+  int want = requested > 0 ? requested : cus * (kCuThreads / kSweepThreads);
   if (driver == CLDIAM_DRIVER_HOST) {
     *blocks = want;
     return CLDIAM_OK;
@@ -1422,6 +1454,13 @@ int grid_blocks(int driver, int requested, int *blocks) {
   }
   *blocks = want < coop_blocks ? want : coop_blocks;
   return CLDIAM_OK;
+}
+
+// Finished workgroups after which the others end their local rounds.
+uint32_t local_cutoff(const cldiam_tuning *tuning, int blocks) {
+  int pct = tuning && tuning->local_cutoff > 0 ? tuning->local_cutoff : kLocalCutoffPct;
+  if (pct > 100) pct = 100;
+  return (uint32_t)(((int64_t)pct * blocks + 99) / 100);
 }
 
 // Descriptor of one graph (node offset set by the caller); returns a status.
@@ -1468,6 +1507,14 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
   const int32_t cf = tuning ? tuning->chunk_factor : 0;
   d.chunk_factor = cf > 0 ? (cf > 64 ? 64 : cf)
                           : ((x.m > (int64_t)kDenseDegree * x.n && x.n > kDenseLarge) ? kDenseChunks : 1);
+  // row tiers (threads per row) and the local queue's size
+  const int32_t wr = tuning ? tuning->wave_row_min : 0, gr = tuning ? tuning->group_row_min : 0;
+  const int32_t lqc = tuning ? tuning->local_queue : 0;
+  const bool dense = x.m > (int64_t)kDenseDegree * x.n;
+  d.mid_deg = wr > 0 ? (wr > (1 << 20) ? (1 << 20) : wr) : (dense ? kDenseWaveRow : kMidDeg);
+  d.big_deg = gr > 0 ? (gr > (1 << 30) ? (1 << 30) : gr) : kBigDeg;
+  if (d.big_deg < d.mid_deg) d.big_deg = d.mid_deg;
+  d.lq_cap = lqc > 0 ? (uint32_t)(lqc < 64 ? 64 : (lqc > kLocalCap ? kLocalCap : lqc)) : (uint32_t)kLocalCap;
   if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
   else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
   else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;
@@ -1590,6 +1637,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   if (!persistent && blocks <= 0) blocks = 256;
   if (blocks > 65535) blocks = 65535;
   job.nblocks = blocks;
+  job.cutoff = local_cutoff(tuning, blocks);
   cld::Pinned<Ctl> pinned;   // readback buffer, back to the pool when the call returns
   Ctl *hc = pinned.p;
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
@@ -1603,7 +1651,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   CLD_HIP(hipEventRecord(ev0, stream));
   if (persistent) {
     void *args[] = {&job};
-    CLD_HIP(hipLaunchCooperativeKernel((const void *)k_persistent, dim3(blocks), dim3(kThreads), args, 0, stream));
+    CLD_HIP(hipLaunchCooperativeKernel((const void *)k_persistent, dim3(blocks), dim3(kSweepThreads), args, 0,
+                                       stream));
     CLD_HIP(hipEventRecord(ev1, stream));
     CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     CLD_HIP(hipStreamSynchronize(stream));
@@ -1615,7 +1664,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     for (;;) {
       for (int i = 0; i < batch; ++i) {
         k_control<<<1, kThreads, 0, stream>>>(job);
-        k_sweep<<<blocks, kThreads, 0, stream>>>(job);
+        k_sweep<<<blocks, kSweepThreads, 0, stream>>>(job);
       }
       CLD_LAUNCH_CHECK("k_sweep");
       CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
@@ -1753,7 +1802,7 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   }
   s->ncap = node_capacity;
   s->gcap = max_graphs;
-  s->tuning = tuning ? *tuning : cldiam_tuning{-1, 0, 0.f, 0};
+  s->tuning = tuning ? *tuning : cldiam_tuning{-1, 0, 0.f, 0, 0, 0, 0, 0, 0};
   s->stream = (hipStream_t)stream;
   Job &job = s->job;
   const Layout &L = s->L;
@@ -1766,6 +1815,7 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   if (rc) { delete s; return rc; }
   if (s->blocks <= 0) s->blocks = 256;
   job.nblocks = s->blocks;
+  job.cutoff = local_cutoff(tuning, s->blocks);
   s->desc.assign(max_graphs, GDesc{});
   s->tag.assign(max_graphs, 0);
   s->active.assign(max_graphs, 0);
@@ -1854,7 +1904,7 @@ extern "C" int cldiam_server_step(cldiam_server *s, int32_t max_sweeps, int32_t 
     CLD_HIP(hipMemsetAsync(&job.ctl->iterations, 0, sizeof(uint32_t), stream));
     for (int i = 0; i < max_sweeps; ++i) {
       k_control<<<1, kThreads, 0, stream>>>(job);
-      k_sweep<<<s->blocks, kThreads, 0, stream>>>(job);
+      k_sweep<<<s->blocks, kSweepThreads, 0, stream>>>(job);
     }
     CLD_LAUNCH_CHECK("k_sweep");
     CLD_HIP(hipMemcpyAsync(s->st_host.data(), job.st, sizeof(GState) * s->gcap, hipMemcpyDeviceToHost, stream));

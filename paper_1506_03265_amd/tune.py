@@ -2,9 +2,13 @@
 
 The knobs it chooses never change results: the driver (host-driven launches
 or one persistent cooperative kernel), the number of workgroup-local
-relaxation rounds per sweep, the number of workgroups per sweep and the
+relaxation rounds per sweep, the number of workgroups per sweep, the
 distance-bucket widths of the relaxation sweeps (all nodes, and nodes with
-long rows) and the number of growth chunks per workgroup.  Each
+long rows: the Delta of the Delta-stepping-style order, not the algorithm's
+initial Delta, which changes results), the number of growth chunks per
+workgroup, the threads per row (rows above a degree go to a wave of 64
+threads, above another to the whole workgroup) and the queue tile of the
+local rounds.  Each
 candidate is timed on the job itself; the outputs of every candidate are
 checked to be identical to the first one's (a schedule that changed a result
 would be a bug).  The choice is cached per workload class (graph count and
@@ -24,6 +28,11 @@ CANDIDATES = (
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, bucket_width=w) for w in (4.0, 16.0, -1.0)]
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, row_bucket_shift=r) for r in (5, 11, -1)]
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, chunk_factor=c) for c in (2, 4)]
+    + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, wave_row_min=w) for w in (8, 128)]
+    + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, group_row_min=g) for g in (1024, 65536)]
+    + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, local_queue=q) for q in (512,)]
+    + [dict(driver=DRIVER_HOST, local_rounds=r, grid_blocks=0, local_cutoff=c) for r, c in ((16, 100), (8, 90),
+                                                                                          (16, 50))]
     + [dict(driver=DRIVER_HOST, local_rounds=4, grid_blocks=128)]
     + [dict(driver=DRIVER_PERSISTENT, local_rounds=r, grid_blocks=128) for r in (0, 4)]
 )

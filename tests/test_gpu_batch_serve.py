@@ -71,6 +71,36 @@ def test_chunk_factor_on_long_rows(chunk_factor, grid_blocks, driver):
     assert (st.stages, st.levels, st.delta_end) == (ref.stages, ref.levels, ref.delta_end)
 
 
+@pytest.mark.parametrize("wave_row_min,group_row_min,local_queue", [(0, 0, 0), (1, 1, 0), (4, 64, 0), (8, 1024, 64),
+                                                                    (128, 65536, 512), (2000, 2000, 4096),
+                                                                    (1 << 20, 1 << 30, 0)])
+def test_row_tiers_and_queue_tile(wave_row_min, group_row_min, local_queue):
+    """Threads per row (one thread, a wave or the whole workgroup, by degree)
+    and the local queue tile only change which threads relax an arc and when:
+    an R-MAT graph with hub rows, a road-like mesh and a batch of both give the
+    oracle's outputs for every setting, for CLUSTER and CLUSTER2, and the
+    literal steps (which use the same tiers) give the oracle's counters."""
+    knobs = dict(wave_row_min=wave_row_min, group_row_min=group_row_min, local_queue=local_queue)
+    _say(f"[systems] row tiers {knobs}")
+    graphs = [graphgen.rmat(13, seed=8), graphgen.road_like(160, 2)]
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    for g, dg in zip(graphs, dgs):
+        for variant in (cd.VARIANT_FIXPOINT, cd.VARIANT_CLUSTER2):
+            ref = oracle.decompose_cluster2(g, 1, 5) if variant else oracle.decompose(g, 1, 5)
+            c, D, st = cd.cldiam_decompose(dg, 1, 5, variant=variant, **knobs)
+            assert np.array_equal(c.cpu().numpy(), ref.cluster), variant
+            assert np.array_equal(cd.u64(D), ref.D), variant
+        ref = oracle.decompose_steps(g, 1, 5)
+        c, D, st = cd.cldiam_decompose(dg, 1, 5, variant=cd.VARIANT_STEPS, **knobs)
+        assert np.array_equal(c.cpu().numpy(), ref.cluster)
+        assert (st.rounds, st.messages, st.updates) == \
+            (ref.work["rounds"], ref.work["messages"], ref.work["updates"])
+    clusters, Ds, stats = cd.cldiam_decompose_batch(dgs, [(2, 11, 0), (2, 12, 0)], **knobs)
+    for g, c, D, (tau, seed) in zip(graphs, clusters, Ds, [(2, 11), (2, 12)]):
+        ref = oracle.decompose(g, tau, seed)
+        assert np.array_equal(c.cpu().numpy(), ref.cluster) and np.array_equal(cd.u64(D), ref.D)
+
+
 @pytest.mark.parametrize("scale,gseed", [(10, 1), (12, 2), (14, 3), (16, 1)])
 def test_rmat_family_under_two_schedules(scale, gseed):
     """R-MAT graphs of several sizes and seeds, CLUSTER and CLUSTER2, under the
