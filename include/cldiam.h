@@ -213,8 +213,17 @@ typedef struct {
                            workgroups have finished the sweep (their work then waits for the next sweep,
                            which spreads it over the whole grid); 1 .. 100 (100: never), 0 = default
                            (75) */
+  int32_t pull_mode;    /* CLDIAM_PULL_*: offers over arcs that became light when Delta grew, and from the
+                           sources of a new stage, can only reach unreached nodes.  In pull mode those
+                           nodes take their best offer from their neighbours (and NEXT is computed from
+                           their side) instead of the blocked nodes pushing to them; it pays when the
+                           blocked nodes outnumber the unreached ones.  CLUSTER2 and the literal steps
+                           never pull. */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
+#define CLDIAM_PULL_AUTO 0    /* switch to pull mode once the blocked nodes outnumber the unreached ones */
+#define CLDIAM_PULL_NEVER 1
+#define CLDIAM_PULL_ALWAYS 2  /* pull from the first stage on */
 
 /* One graph description of a batch (graph operand in DEVICE memory). */
 typedef struct {

@@ -26,6 +26,7 @@ CLDIAM_EHIP = -4
 CLDIAM_ESTAGES = -5
 CLDIAM_ETIMEOUT = -6
 CLDIAM_NOALLOC_MAX_K = 32768   # largest quotient of cldiam_estimate_diameter_noalloc
+PULL_AUTO, PULL_NEVER, PULL_ALWAYS = 0, 1, 2
 STAGE_LOG = 64
 
 DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
@@ -69,7 +70,7 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("local_rounds", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("bucket_width", ctypes.c_float),
                 ("row_bucket_shift", ctypes.c_int32), ("chunk_factor", ctypes.c_int32),
                 ("wave_row_min", ctypes.c_int32), ("group_row_min", ctypes.c_int32), ("local_queue", ctypes.c_int32),
-                ("local_cutoff", ctypes.c_int32)]
+                ("local_cutoff", ctypes.c_int32), ("pull_mode", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -256,7 +257,8 @@ class DecomposeJob:
     allocated once so that repeated runs time only the device work."""
 
     def __init__(self, graphs, params, driver=DRIVER_AUTO, local_rounds=-1, grid_blocks=0, bucket_width=0.0,
-                 row_bucket_shift=0, chunk_factor=0, wave_row_min=0, group_row_min=0, local_queue=0, local_cutoff=0):
+                 row_bucket_shift=0, chunk_factor=0, wave_row_min=0, group_row_min=0, local_queue=0, local_cutoff=0,
+                 pull_mode=0):
         torch = _torch()
         self.lib = load_library()
         self.graphs = list(graphs)
@@ -277,7 +279,7 @@ class DecomposeJob:
         self.ws = _ws(self.wsb, dev)
         self.driver = driver
         self.tuning = _Tuning(local_rounds, grid_blocks, bucket_width, row_bucket_shift, chunk_factor, wave_row_min,
-                              group_row_min, local_queue, local_cutoff)
+                              group_row_min, local_queue, local_cutoff, pull_mode)
 
     def run(self, stream=None):
         _check(self.lib.cldiam_decompose_batch(len(self.graphs), self.desc, self.stats, self.driver,
@@ -288,23 +290,23 @@ class DecomposeJob:
 
 def cldiam_decompose(g: DeviceGraph, tau: int, seed: int, delta0: int = 0, driver=DRIVER_AUTO, stream=None,
                      local_rounds=-1, grid_blocks=0, bucket_width=0.0, variant=0, step_cap=0, row_bucket_shift=0,
-                     chunk_factor=0, wave_row_min=0, group_row_min=0, local_queue=0, local_cutoff=0):
+                     chunk_factor=0, wave_row_min=0, group_row_min=0, local_queue=0, local_cutoff=0, pull_mode=0):
     """CLUSTER(G, tau): returns (cluster int32 tensor, D int64 tensor holding
     uint64 bit patterns, Stats).  variant = VARIANT_STEPS runs PartialGrowth
     literally (synchronous steps, per-step stop, optional step cap)."""
     job = DecomposeJob([g], [(tau, seed, delta0, variant, step_cap)], driver, local_rounds, grid_blocks,
                        bucket_width, row_bucket_shift, chunk_factor, wave_row_min, group_row_min, local_queue,
-                       local_cutoff)
+                       local_cutoff, pull_mode)
     st = job.run(stream)
     return job.cluster[0], job.D[0], st[0]
 
 
 def cldiam_decompose_batch(graphs, params, driver=DRIVER_AUTO, stream=None, local_rounds=-1, grid_blocks=0,
                            bucket_width=0.0, row_bucket_shift=0, chunk_factor=0, wave_row_min=0, group_row_min=0,
-                           local_queue=0, local_cutoff=0):
+                           local_queue=0, local_cutoff=0, pull_mode=0):
     """Decomposes many graphs in one device job; params = [(tau, seed, delta0[, variant, step_cap])]."""
     job = DecomposeJob(graphs, params, driver, local_rounds, grid_blocks, bucket_width, row_bucket_shift,
-                       chunk_factor, wave_row_min, group_row_min, local_queue, local_cutoff)
+                       chunk_factor, wave_row_min, group_row_min, local_queue, local_cutoff, pull_mode)
     st = job.run(stream)
     return job.cluster, job.D, st
 
@@ -320,7 +322,7 @@ class Server:
     def __init__(self, node_capacity: int, max_graphs: int = 64, local_rounds: int = -1, grid_blocks: int = 0,
                  bucket_width: float = 0.0, row_bucket_shift: int = 0, chunk_factor: int = 0, device="cuda",
                  stream=None, wave_row_min: int = 0, group_row_min: int = 0, local_queue: int = 0,
-                 local_cutoff: int = 0):
+                 local_cutoff: int = 0, pull_mode: int = 0):
         torch = _torch()
         self.lib = load_library()
         self.device = device
@@ -331,7 +333,7 @@ class Server:
         _check(self.lib.cldiam_server_create(ctypes.byref(self.ptr), node_capacity, max_graphs,
                                              ctypes.byref(_Tuning(local_rounds, grid_blocks, bucket_width, row_bucket_shift,
                                                                   chunk_factor, wave_row_min, group_row_min,
-                                                                  local_queue, local_cutoff)),
+                                                                  local_queue, local_cutoff, pull_mode)),
                                              _ptr(self.ws), self.wsb,
                                              ctypes.c_void_p(self.stream.cuda_stream)), "cldiam_server_create")
         self.outputs = {}

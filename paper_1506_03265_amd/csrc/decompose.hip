@@ -88,6 +88,8 @@ enum Phase : uint32_t {
   PH_C2_SELECT = 13,    // CLUSTER2: centers of iteration i with probability 2^i / n
   PH_C2_BOUNDARY = 14,  // CLUSTER2: Contract2's rescaled edges out of last iteration's clusters
   PH_C2_ASSIGN = 15,    // CLUSTER2: assignment, D = d + Delta2 (i - birth iteration)
+  PH_PULL = 16,         // pull mode: unreached nodes take their best offer from reached neighbours
+  PH_NEXT_PULL = 17,    // pull mode: NEXT computed from the unreached nodes' side
 };
 
 struct GDesc {
@@ -111,6 +113,7 @@ struct GDesc {
   int32_t mid_deg;       // rows of more arcs are relaxed by one wave ("long rows")
   int32_t big_deg;       // rows of more arcs are relaxed by the whole workgroup
   uint32_t lq_cap;       // slots of the local relaxation queue used (at most kLocalCap)
+  uint32_t pull_mode;    // CLDIAM_PULL_*: when new levels and stages pull from the unreached side
 };
 
 // Control-owned state of one graph.
@@ -130,6 +133,8 @@ struct GState {
   uint32_t c2;          // 1 while in CLUSTER2's iterations
   uint64_t rounds, updates;
   uint64_t radius1;     // CLUSTER2: R_CL of the preliminary CLUSTER run
+  uint32_t pull;        // 1 once the graph grows new levels and stages by pulling (see PH_PULL)
+  uint32_t pull_base;   // distance at which the current pulled level starts (its first bucket)
 };
 
 struct alignas(128) PadU32 {
@@ -217,16 +222,27 @@ constexpr uint32_t kPassChunk = kSweepThreads;   // smallest chunk of a node pas
 
 // ------------------------------------------------------------- control --
 
+// Which counter holds the items of a phase's sweep, 3 bits per phase.  A
+// table and two selects rather than a switch: the switch form (cases sharing
+// a counter) compiled, for one phase, into divergent branches that never set
+// the counter's address.
+enum : uint32_t { IT_NONE = 0, IT_U = 1, IT_FCUR = 2, IT_BLK = 3, IT_FNXT = 4 };
+constexpr uint64_t item_kind(uint32_t phase, uint32_t kind) { return (uint64_t)kind << (3 * phase); }
+constexpr uint64_t kItemTable =
+    item_kind(PH_SELECT, IT_U) | item_kind(PH_COMPACT, IT_U) | item_kind(PH_SINGLE, IT_U) |
+    item_kind(PH_ASSIGN, IT_U) | item_kind(PH_RMAX, IT_U) | item_kind(PH_RELAX, IT_FCUR) |
+    item_kind(PH_NEXT, IT_BLK) | item_kind(PH_MERGE, IT_BLK) | item_kind(PH_COMMIT, IT_FNXT) |
+    item_kind(PH_C2_SELECT, IT_U) | item_kind(PH_C2_ASSIGN, IT_U) | item_kind(PH_C2_BOUNDARY, IT_BLK) |
+    item_kind(PH_PULL, IT_U) | item_kind(PH_NEXT_PULL, IT_U);
+static_assert(3 * PH_NEXT_PULL + 3 <= 64, "item table holds every phase");
+
 __device__ uint32_t items_of(const GState &s, const GCount &c) {
-  switch (s.phase) {
-    case PH_SELECT: case PH_COMPACT: case PH_SINGLE: case PH_ASSIGN: case PH_RMAX: return c.cntU[s.ucur].v;
-    case PH_RELAX: return c.cnt[s.fcur].v;
-    case PH_NEXT: case PH_MERGE: return c.cnt[s.blk].v;
-    case PH_COMMIT: return c.cnt[s.fnxt].v;
-    case PH_C2_SELECT: case PH_C2_ASSIGN: return c.cntU[s.ucur].v;
-    case PH_C2_BOUNDARY: return c.cnt[s.blk].v;
-    default: return 0;
-  }
+  const uint32_t p = s.phase;
+  const uint32_t kind = p <= PH_NEXT_PULL ? (uint32_t)(kItemTable >> (3 * p)) & 7u : IT_NONE;
+  if (kind == IT_NONE) return 0;
+  const uint32_t idx = kind == IT_FCUR ? s.fcur : (kind == IT_BLK ? s.blk : (kind == IT_FNXT ? s.fnxt : s.ucur));
+  const PadU32 *list = kind == IT_U ? c.cntU : c.cnt;
+  return list[idx].v;
 }
 
 // A failing graph stops alone; the other graphs of the job go on.
@@ -321,6 +337,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       c.cnt[0].v = c.cnt[1].v = c.cnt[2].v = 0;
       c.radius.v = 0;
       if ((uint64_t)s.delta > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); break; }
+      s.pull = d.pull_mode == CLDIAM_PULL_ALWAYS && d.variant == CLDIAM_VARIANT_FIXPOINT ? 1u : 0u;
       begin_stage(d, s, c, job.ctl);
       break;
     case PH_SELECT:
@@ -333,10 +350,24 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         begin_call(s, sweep_id);
         break;
       }
-      s.level_id = sweep_id;
       s.levels++;
+      if (s.pull) {
+        // the uncovered nodes pull from the assigned nodes and the new centers
+        s.pull_base = 0;
+        s.phase = PH_PULL;
+        break;
+      }
+      s.level_id = sweep_id;
       s.theta = bucket_limit(d, 0);
       s.row_base = 0;
+      c.fmin.v = 0xffffffffu;
+      s.phase = PH_RELAX;
+      break;
+    case PH_PULL:
+      // the pulled nodes are the frontier of the level
+      s.level_id = sweep_id;
+      s.theta = bucket_limit(d, s.pull_base);
+      s.row_base = s.pull_base;
       c.fmin.v = 0xffffffffu;
       s.phase = PH_RELAX;
       break;
@@ -361,7 +392,13 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         c.cnt[s.fcur].v = 0;
         if (s.c2) s.phase = PH_C2_ASSIGN;
         else if (2ull * c.cntC.v >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
-        else { c.next.v = CLD_INF64; s.phase = PH_NEXT; }
+        else {
+          // pull from the unreached side once the blocked list (whose rows a
+          // push rescan reads) outnumbers the unreached nodes
+          if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && c.cnt[s.blk].v > s.nU - c.cntC.v) s.pull = 1;
+          c.next.v = CLD_INF64;
+          s.phase = s.pull ? PH_NEXT_PULL : PH_NEXT;
+        }
       }
       break;
     case PH_COMMIT: {
@@ -416,6 +453,22 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         s.phase = PH_RELAX;
       }
       break;
+    case PH_NEXT_PULL:
+      if (c.next.v == CLD_INF64) {
+        s.phase = PH_ASSIGN;
+      } else {
+        uint64_t dl = s.delta;
+        do {
+          if (2 * dl > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); return; }
+          dl *= 2;
+          s.levels++;
+        } while (dl < c.next.v);
+        s.delta = (uint32_t)dl;
+        c.cnt[s.blk].v = 0;
+        s.pull_base = (uint32_t)c.next.v;
+        s.phase = PH_PULL;
+      }
+      break;
     case PH_ASSIGN:
       s.phase = PH_RMAX;
       break;
@@ -440,8 +493,12 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         break;
       }
       if (d.variant != CLDIAM_VARIANT_STEPS) {
-        // sources of the next stage: the blocked list of the last level
-        uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
+        // sources of the next stage: the blocked list of the last level, or,
+        // when it outnumbers the remaining uncovered nodes, none: those
+        // nodes pull from their assigned neighbours instead
+        if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && c.cnt[s.blk].v > c.cntU[s.ucur].v) s.pull = 1;
+        if (!s.pull) { uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t; }
+        else c.cnt[s.fcur].v = 0;
       }
       // (synchronous steps: the active list, merged with the blocked list,
       // already holds them)
@@ -461,6 +518,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         s.delta = (uint32_t)(2 * r1);
         if (d.c2_iters == 0) break;   // one node: its own cluster
         s.c2 = 1;
+        s.pull = 0;
         s.stage = 0;
         s.levels = 0;
         s.centers_total = 0;
@@ -528,7 +586,7 @@ __device__ void control_block(const Job &job) {
       // millions of cheap items beside a small frontier of costly rows).
       uint32_t per = 0;
       if (n_items) {
-        const bool grow = phase == PH_RELAX || phase == PH_NEXT;
+        const bool grow = phase == PH_RELAX || phase == PH_NEXT || phase == PH_PULL || phase == PH_NEXT_PULL;
         const uint32_t nch = (uint32_t)job.nblocks * (grow ? (uint32_t)job.desc[g].chunk_factor : 1u);
         per = (n_items + nch - 1) / nch;
         if (!grow && per < kPassChunk) per = kPassChunk;
@@ -1014,6 +1072,136 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
   return scanned;
 }
 
+// Pull mode.  Offers over arcs that were heavy at the previous Delta, or
+// from the sources of a new stage, can only reach unreached nodes: they are
+// at least the previous Delta, above every reached key.  When the unreached
+// nodes are fewer than the blocked ones, they look at their neighbours
+// instead: PULL gives an unreached node v the lexicographic minimum over its
+// neighbours u with a key of (d_u + w, c_u), d_u + w <= Delta (only v's own
+// thread writes v's key, so no atomic is needed); NEXT_PULL folds the smallest
+// d_u + w over the same arcs into S.acc.  Rows are sorted by weight, so PULL
+// stops past Delta (d_u >= 0) and NEXT_PULL once w reaches the best value.
+// A key read while its node is being pulled in the same pass is a real path
+// too, so taking it only moves the fixpoint closer.
+
+// Value of one arc (pull) or distance (next) offered to an unreached node.
+__device__ __forceinline__ uint64_t pull_offer(const Job &job, int64_t off, uint64_t arc, uint32_t delta, bool next) {
+  const uint64_t k = job.key[off + (int32_t)(uint32_t)arc];
+  if (k == CLD_INF64) return CLD_INF64;
+  const uint64_t du = k >> 32, w = arc >> 32;
+  if (next) return du + w;
+  return du + w <= delta ? k + (w << 32) : CLD_INF64;
+}
+
+__device__ __forceinline__ void pull_apply(const Job &job, int64_t off, int32_t v, uint64_t best, bool next, Stage &S,
+                                           const Out *out) {
+  if (next) {
+    if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
+  } else if (best != CLD_INF64) {
+    job.key[off + v] = best;
+    stage_push(S, out, 0, v);
+    stage_push(S, out, 1, v);
+  }
+}
+
+// One node of the uncovered list, its row scanned by this thread (long rows
+// are deferred to a wave or to the workgroup).
+__device__ __forceinline__ void pull_item(const Job &job, const GDesc &d, int64_t off, uint32_t delta, int32_t v,
+                                          bool next, Stage &S, const Out *out) {
+  if (job.key[off + v] != CLD_INF64) return;
+  const int64_t a0 = d.row_ptr[v];
+  const int32_t deg = (int32_t)(d.row_ptr[v + 1] - a0);
+  if (deg > d.mid_deg && defer_row(S, v, deg, d.big_deg)) return;
+  const uint64_t *row = d.arcs + a0;
+  uint64_t best = CLD_INF64;
+  for (int32_t base = 0; base < deg; base += kArcBatch) {
+    uint64_t arc[kArcBatch];
+    bool ok[kArcBatch];
+    bool stop = false;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) arc[j] = base + j < deg ? row[base + j] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) {
+      const uint64_t w = arc[j] >> 32;
+      ok[j] = base + j < deg && (next ? w < best : w <= delta);
+      if (base + j < deg && !ok[j]) stop = true;
+    }
+    uint64_t c[kArcBatch];
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) c[j] = ok[j] ? pull_offer(job, off, arc[j], delta, next) : CLD_INF64;
+#pragma unroll
+    for (int j = 0; j < kArcBatch; ++j) best = c[j] < best ? c[j] : best;
+    if (stop) break;
+  }
+  pull_apply(job, off, v, best, next, S, out);
+}
+
+__device__ __forceinline__ uint64_t wave_min_all(uint64_t x) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t y = __shfl_xor(x, o);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// The long rows deferred by pull_item: a wave per row, then the whole
+// workgroup per hub row.
+__device__ void pull_rows(const Job &job, const GDesc &d, int64_t off, uint32_t delta, bool next, Stage &S,
+                          const Out *out) {
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t nm = S.mid_cnt < kMidCap ? S.mid_cnt : kMidCap;
+  const uint32_t nb = S.big_cnt < kBigCap ? S.big_cnt : kBigCap;
+  for (uint32_t r = wave; r < nm; r += nwaves) {
+    const int32_t v = S.mid[r];
+    const int64_t a0 = d.row_ptr[v];
+    const int32_t a1 = (int32_t)(d.row_ptr[v + 1] - a0);
+    const uint64_t *row = d.arcs + a0;
+    uint64_t best = CLD_INF64;
+    for (int32_t base = 0; base < a1; base += 64) {
+      const int32_t a = base + (int32_t)lane;
+      const uint64_t arc = a < a1 ? row[a] : ~0ull;
+      const uint64_t w = arc >> 32;
+      const bool in = a < a1 && (next ? w < best : w <= delta);
+      if (!__any(in)) break;
+      const uint64_t m = wave_min_all(in ? pull_offer(job, off, arc, delta, next) : CLD_INF64);
+      best = m < best ? m : best;
+    }
+    if (lane == 0) pull_apply(job, off, v, best, next, S, out);
+  }
+  for (uint32_t h = 0; h < nb; ++h) {
+    const int32_t v = S.big[h];
+    const int64_t a0 = d.row_ptr[v];
+    const int32_t a1 = (int32_t)(d.row_ptr[v + 1] - a0);
+    const uint64_t *row = d.arcs + a0;
+    if (threadIdx.x == 0) S.blk_min = CLD_INF64;
+    __syncthreads();
+    for (int32_t base = 0; base < a1; base += (int32_t)blockDim.x) {
+      const uint64_t cur = S.blk_min;   // the same for every thread: nothing changes it between the barriers
+      const int32_t a = base + (int32_t)threadIdx.x;
+      if (a < a1) {
+        const uint64_t arc = row[a];
+        const uint64_t w = arc >> 32;
+        if (next ? w < cur : w <= delta) {
+          const uint64_t c = pull_offer(job, off, arc, delta, next);
+          if (c < cur) atomicMin(&S.blk_min, (unsigned long long)c);
+        }
+      }
+      __syncthreads();
+      const int32_t nxt = base + (int32_t)blockDim.x;
+      const uint64_t cur2 = S.blk_min;
+      const bool stop = nxt >= a1 || (next ? (row[nxt] >> 32) >= cur2 : (row[nxt] >> 32) > delta);
+      __syncthreads();   // every thread has read S.blk_min before the next chunk changes it
+      if (stop) break;
+    }
+    if (threadIdx.x == 0) pull_apply(job, off, v, S.blk_min, next, S, out);
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) { S.mid_cnt = 0; S.big_cnt = 0; }
+  __syncthreads();
+}
+
 // CLUSTER2, Contract2: u was assigned last iteration at growth distance dl
 // (kept in keyn) with label c; every edge with Delta2 - dl < w <= Delta2 is
 // the rescaled edge (c, v) of weight dl + w - Delta2.  Rows are sorted by
@@ -1082,6 +1270,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       o[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
       nout = 1;
       break;
+    case PH_PULL:
     case PH_C2_SELECT:
     case PH_C2_BOUNDARY:
       o[0] = {job.pool[fcur] + off, &cn.cnt[fcur].v};
@@ -1097,7 +1286,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.out[0] = o[0];
     S.out[1] = o[1];
     S.out[2] = o[2];
-    S.acc = (phase == PH_NEXT) ? CLD_INF64 : 0ull;
+    S.acc = (phase == PH_NEXT || phase == PH_NEXT_PULL) ? CLD_INF64 : 0ull;
     S.acc32 = 0;
     S.fmin = 0xffffffffu;
     S.lq_cnt[0] = 0;
@@ -1184,6 +1373,10 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           if (best < S.acc) atomicMin(&S.acc, (unsigned long long)best);
           break;
         }
+        case PH_PULL:
+        case PH_NEXT_PULL:
+          pull_item(job, d, off, delta, job.U[ucur][off + idx], phase == PH_NEXT_PULL, S, out);
+          break;
         case PH_ASSIGN: {
           // over the stage's uncovered list (in node order at the first
           // stage, so these reads and writes are coalesced); covered nodes
@@ -1225,6 +1418,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           break;
       }
     }
+    if (phase == PH_PULL || phase == PH_NEXT_PULL) pull_rows(job, d, off, delta, phase == PH_NEXT_PULL, S, out);
     if (phase == PH_RELAX || phase == PH_NEXT)
       scanned += coop_rows(job, d, off, delta, it, level_id, S, out, steps ? nullptr : &S.lq_cnt[0],
                            steps ? nullptr : S.lq[0], phase == PH_NEXT ? 1 : (steps ? 2 : 0), resume);
@@ -1269,7 +1463,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   if (nout) stage_flush(S, out, nout);
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (phase == PH_NEXT && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
+    if ((phase == PH_NEXT || phase == PH_NEXT_PULL) && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
     if ((phase == PH_ASSIGN || phase == PH_C2_ASSIGN) && S.acc) atomicMax(&cn.radius.v, S.acc);
     if ((phase == PH_SELECT || phase == PH_C2_SELECT) && S.acc32) atomicAdd(&cn.centers.v, S.acc32);
     if (phase == PH_RELAX && S.fmin != 0xffffffffu) atomicMin(&cn.fmin.v, S.fmin);
@@ -1515,6 +1709,12 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
   d.big_deg = gr > 0 ? (gr > (1 << 30) ? (1 << 30) : gr) : kBigDeg;
   if (d.big_deg < d.mid_deg) d.big_deg = d.mid_deg;
   d.lq_cap = lqc > 0 ? (uint32_t)(lqc < 64 ? 64 : (lqc > kLocalCap ? kLocalCap : lqc)) : (uint32_t)kLocalCap;
+  const int32_t pm = tuning ? tuning->pull_mode : 0;
+  if (pm < 0 || pm > CLDIAM_PULL_ALWAYS) {
+    cld::set_error("decompose: unknown pull mode %d (graph %d)", pm, g);
+    return CLDIAM_EINVAL;
+  }
+  d.pull_mode = (uint32_t)pm;
   if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
   else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
   else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;
@@ -1802,7 +2002,7 @@ extern "C" int cldiam_server_create(cldiam_server **out, int64_t node_capacity, 
   }
   s->ncap = node_capacity;
   s->gcap = max_graphs;
-  s->tuning = tuning ? *tuning : cldiam_tuning{-1, 0, 0.f, 0, 0, 0, 0, 0, 0};
+  s->tuning = tuning ? *tuning : cldiam_tuning{-1, 0, 0.f, 0, 0, 0, 0, 0, 0, 0};
   s->stream = (hipStream_t)stream;
   Job &job = s->job;
   const Layout &L = s->L;

@@ -94,7 +94,7 @@ def test_python_structures_match_the_header(tmp_path):
         "cldiam_params": (cd._Params, ["tau", "delta0", "seed", "variant", "step_cap"]),
         "cldiam_tuning": (cd._Tuning, ["local_rounds", "grid_blocks", "bucket_width", "row_bucket_shift",
                                         "chunk_factor", "wave_row_min", "group_row_min", "local_queue",
-                                        "local_cutoff"]),
+                                        "local_cutoff", "pull_mode"]),
         "cldiam_graph": (cd._Graph, ["m", "d_arcs", "weight_sum", "params", "d_cluster", "d_D"]),
         "cldiam_stats": (cd._Stats, ["stages", "radius", "arcs_scanned", "status", "kernel_ms", "iterations",
                                      "rounds", "messages", "updates", "radius1", "stage_uncovered",

@@ -289,3 +289,73 @@ def test_engine_serving_equals_alone_results():
         assert bool((a.cluster == b.cluster).all()) and bool((a.D == b.D).all())
         assert (a.num_clusters, a.radius, a.phi_gc, a.phi_approx) == (b.num_clusters, b.radius, b.phi_gc, b.phi_approx)
         assert a.latency_s >= 0
+
+
+def _pull_families():
+    rng = np.random.default_rng(31)
+    fams = [("grid_small", graphgen.grid_small()), ("road200", graphgen.road_like(200, 7)),
+            ("rmat12", graphgen.rmat(12, seed=4)), ("rmat15", graphgen.rmat(15, seed=6)),
+            ("bimodal128", graphgen.bimodal_mesh(128, 3))]
+    for i in range(3):
+        n = int(rng.integers(150, 400))
+        fams.append((f"er{i}", graphgen.random_small(rng, n, 0.03, int(rng.choice([2, 100, 10000])),
+                                                    connected=bool(i % 2))))
+    n = 300
+    fams.append(("star", graphgen.csr_from_edges_np(n, [0] * (n - 1), range(1, n), list(range(1, n)))))
+    fams.append(("twocomp", graphgen.csr_from_edges_np(200, list(range(99)) + list(range(100, 199)),
+                                                       list(range(1, 100)) + list(range(101, 200)), [3] * 198)))
+    return fams
+
+
+PULL_FAMILIES = _pull_families()
+
+
+@pytest.mark.parametrize("pull_mode", [cd.PULL_NEVER, cd.PULL_ALWAYS, cd.PULL_AUTO], ids=["never", "always", "auto"])
+@pytest.mark.parametrize("name,g", PULL_FAMILIES, ids=[f for f, _ in PULL_FAMILIES])
+def test_pull_mode_equals_oracle(name, g, pull_mode):
+    """New levels and stages grown by pulling from the unreached side (the
+    unreached nodes take their best offer from their neighbours, and NEXT is
+    computed from their side) give the oracle's outputs on every family, for
+    several tau, seeds and initial Delta (small ones force many levels), and
+    CLUSTER2 (which never pulls) is unaffected by the knob."""
+    dg = cd.cldiam_load_csr(g)
+    _say(f"[systems] pull mode {pull_mode} on {name} n={g.n}")
+    for tau, seed, d0 in ((1, 3, 0), (2, 8, 1), (4, 5, 0)):
+        ref = oracle.decompose(g, tau, seed, delta0=d0)
+        c, D, st = cd.cldiam_decompose(dg, tau, seed, delta0=d0, pull_mode=pull_mode)
+        assert np.array_equal(c.cpu().numpy(), ref.cluster), (tau, seed, d0)
+        assert np.array_equal(cd.u64(D), ref.D), (tau, seed, d0)
+        assert (st.stages, st.levels, st.delta_end, st.num_clusters, st.radius) == \
+            (ref.stages, ref.levels, ref.delta_end, ref.num_clusters, ref.radius), (tau, seed, d0)
+    ref = oracle.decompose_cluster2(g, 1, 2)
+    c, D, st = cd.cldiam_decompose(dg, 1, 2, variant=cd.VARIANT_CLUSTER2, pull_mode=pull_mode)
+    assert np.array_equal(c.cpu().numpy(), ref.cluster) and np.array_equal(cd.u64(D), ref.D)
+
+
+def test_pull_mode_in_a_batch_and_a_server():
+    """A batch mixing graphs that pull and graphs that push, and the same
+    graphs served through the continuous-batching server: the oracle's
+    outputs for each."""
+    graphs = [graphgen.rmat(13, seed=9), graphgen.road_like(150, 4), graphgen.rmat(11, seed=3)]
+    dgs = [cd.cldiam_load_csr(g) for g in graphs]
+    params = [(1, 21, 0), (2, 22, 1), (1, 23, 0)]
+    for pm in (cd.PULL_ALWAYS, cd.PULL_AUTO):
+        _say(f"[systems] pull mode {pm} in a batch")
+        clusters, Ds, stats = cd.cldiam_decompose_batch(dgs, params, pull_mode=pm)
+        for g, c, D, (tau, seed, d0) in zip(graphs, clusters, Ds, params):
+            ref = oracle.decompose(g, tau, seed, delta0=d0)
+            assert np.array_equal(c.cpu().numpy(), ref.cluster) and np.array_equal(cd.u64(D), ref.D)
+    srv = cd.Server(sum(g.n for g in graphs), max_graphs=2, pull_mode=cd.PULL_ALWAYS)
+    for i, (dg, (tau, seed, d0)) in enumerate(zip(dgs, params)):
+        srv.submit(dg, tau, seed, i, delta0=d0)
+    done = {}
+    for _ in range(10000):
+        act, queued = srv.step(8)
+        for tag, st, _g, cl, D in srv.poll():
+            done[tag] = (cl, D)
+        if len(done) == len(graphs):
+            break
+    assert len(done) == len(graphs)
+    for i, (g, (tau, seed, d0)) in enumerate(zip(graphs, params)):
+        ref = oracle.decompose(g, tau, seed, delta0=d0)
+        assert np.array_equal(done[i][0].cpu().numpy(), ref.cluster) and np.array_equal(cd.u64(done[i][1]), ref.D)

@@ -66,6 +66,18 @@ def test_road4096_decompose_quotient_estimate(road, driver):
     assert (phi, approx) == (counts["phi_gc"], counts["phi_approx"])
 
 
+def test_road4096_pulling_from_the_first_stage(road):
+    """Every level and stage grown by pulling from the unreached side (the
+    mesh never switches by itself): the same digests."""
+    g, counts, dg = road
+    print("[fullsize] road4096 pull mode always", file=sys.stderr, flush=True)
+    cluster, D, st = cd.cldiam_decompose(dg, counts["tau"], counts["seed"], pull_mode=cd.PULL_ALWAYS)
+    assert (st.stages, st.levels, st.delta_end, st.num_clusters, st.radius) == \
+        (counts["stages"], counts["levels"], counts["delta_end"], counts["num_clusters"], counts["radius"])
+    assert _digest(cluster.cpu().numpy()) == counts["cluster_sha256"]
+    assert _digest(cd.u64(D)) == counts["D_sha256"]
+
+
 def test_road4096_sssp_equals_dijkstra(road):
     """The competitor's Delta-stepping distances from the source rule, with
     the default bucket width and with the benchmark's best, against the
