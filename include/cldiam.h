@@ -215,13 +215,15 @@ typedef struct {
                            (75) */
   int32_t pull_mode;    /* CLDIAM_PULL_*: offers over arcs that became light when Delta grew, and from the
                            sources of a new stage, can only reach unreached nodes.  In pull mode those
-                           nodes take their best offer from their neighbours (and NEXT is computed from
-                           their side) instead of the blocked nodes pushing to them; it pays when the
-                           blocked nodes outnumber the unreached ones.  CLUSTER2 and the literal steps
-                           never pull. */
+                           nodes take their best offer from their neighbours, reading keys written
+                           earlier in the same pass (and NEXT is computed from their side), instead of
+                           the blocked nodes pushing to them.  Results are the same in every mode.
+                           CLUSTER2 and the literal steps never pull. */
 } cldiam_tuning;
 #define CLDIAM_BUCKET_DEFAULT 8.0f
-#define CLDIAM_PULL_AUTO 0    /* switch to pull mode once the blocked nodes outnumber the unreached ones */
+#define CLDIAM_PULL_AUTO 0    /* pull from the first stage on when rows of more than 8x the average degree
+                                 hold more than 1/8 of the arcs; else switch to pull mode once the heavy
+                                 arcs of the blocked rows exceed 8 per unreached node */
 #define CLDIAM_PULL_NEVER 1
 #define CLDIAM_PULL_ALWAYS 2  /* pull from the first stage on */
 

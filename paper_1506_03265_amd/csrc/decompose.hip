@@ -114,6 +114,8 @@ struct GDesc {
   int32_t big_deg;       // rows of more arcs are relaxed by the whole workgroup
   uint32_t lq_cap;       // slots of the local relaxation queue used (at most kLocalCap)
   uint32_t pull_mode;    // CLDIAM_PULL_*: when new levels and stages pull from the unreached side
+  uint32_t hub_deg;      // rows of more arcs are hub rows (kHubDegree x the average degree)
+  uint64_t hub_min;      // more arcs than this in hub rows: a skewed, low-diameter graph
 };
 
 // Control-owned state of one graph.
@@ -156,6 +158,8 @@ struct GCount {
   PadU64 radius;   // max D
   PadU32 fmin;     // RELAX: smallest tentative distance pushed on the next frontier
   PadU64 msgs;     // synchronous steps: offers sent
+  PadU64 blk_arcs; // heavy arcs left on the rows of the blocked list (what a push rescan would read)
+  PadU64 hub_arcs; // first SELECT (auto pull mode): arcs in hub rows
 };
 
 struct Ctl {
@@ -219,6 +223,9 @@ constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 constexpr uint32_t kPassChunk = kSweepThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
+constexpr uint32_t kPullArcs = 8;   // pull-mode switch: heavy blocked arcs per unreached node
+constexpr int64_t kHubDegree = 8;   // hub rows: more than kHubDegree x the average degree ...
+constexpr int64_t kHubShare = 8;    // ... holding more than 1/kHubShare of the arcs: pull from the first stage
 
 // ------------------------------------------------------------- control --
 
@@ -312,6 +319,14 @@ __device__ __forceinline__ void merge_then(GState &s, uint32_t after) {
   s.phase = PH_MERGE;
 }
 
+// Pull mode pays once the heavy arcs of the blocked rows, which a push rescan
+// and a push NEXT read, outweigh kPullArcs arcs per unreached node (about
+// what pulling reads per node: its rows are sorted by weight and it stops at
+// its first reached neighbour).
+__device__ __forceinline__ bool pull_pays(const GCount &c, uint32_t unreached) {
+  return c.blk_arcs.v > (unsigned long long)kPullArcs * unreached;
+}
+
 __device__ __forceinline__ bool double_delta(GState &s, Ctl *ctl) {
   if (2ull * s.delta > CLD_DELTA_MAX) {
     fail(s, ctl, CLDIAM_EOVERFLOW);
@@ -335,9 +350,11 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
       s.ucur = 0;
       s.fcur = 0; s.fnxt = 1; s.blk = 2;
       c.cnt[0].v = c.cnt[1].v = c.cnt[2].v = 0;
+      c.blk_arcs.v = 0;
+      c.hub_arcs.v = 0;
       c.radius.v = 0;
       if ((uint64_t)s.delta > CLD_DELTA_MAX) { fail(s, job.ctl, CLDIAM_EOVERFLOW); break; }
-      s.pull = d.pull_mode == CLDIAM_PULL_ALWAYS && d.variant == CLDIAM_VARIANT_FIXPOINT ? 1u : 0u;
+      s.pull = d.pull_mode == CLDIAM_PULL_ALWAYS ? 1u : 0u;
       begin_stage(d, s, c, job.ctl);
       break;
     case PH_SELECT:
@@ -351,6 +368,10 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         break;
       }
       s.levels++;
+      // a skewed degree distribution (hub rows holding a large share of the
+      // arcs) goes with a low diameter: the growth then reaches most nodes
+      // within a few hops, which a pull pass does for less than pushing
+      if (!s.pull && s.stage == 0 && d.pull_mode == CLDIAM_PULL_AUTO && c.hub_arcs.v > d.hub_min) s.pull = 1;
       if (s.pull) {
         // the uncovered nodes pull from the assigned nodes and the new centers
         s.pull_base = 0;
@@ -393,9 +414,9 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         if (s.c2) s.phase = PH_C2_ASSIGN;
         else if (2ull * c.cntC.v >= (uint64_t)s.nU) s.phase = PH_ASSIGN;
         else {
-          // pull from the unreached side once the blocked list (whose rows a
-          // push rescan reads) outnumbers the unreached nodes
-          if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && c.cnt[s.blk].v > s.nU - c.cntC.v) s.pull = 1;
+          // pull from the unreached side once the heavy arcs of the blocked
+          // rows (what a push rescan reads) outweigh the unreached nodes
+          if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && pull_pays(c, s.nU - c.cntC.v)) s.pull = 1;
           c.next.v = CLD_INF64;
           s.phase = s.pull ? PH_NEXT_PULL : PH_NEXT;
         }
@@ -446,6 +467,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         // rescan the blocked nodes at the new Delta; fresh blocked list
         uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t;
         c.cnt[s.blk].v = 0;
+        c.blk_arcs.v = 0;
         s.level_id = sweep_id;
         s.theta = bucket_limit(d, (uint32_t)c.next.v);
         s.row_base = (uint32_t)c.next.v;
@@ -465,6 +487,7 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         } while (dl < c.next.v);
         s.delta = (uint32_t)dl;
         c.cnt[s.blk].v = 0;
+        c.blk_arcs.v = 0;
         s.pull_base = (uint32_t)c.next.v;
         s.phase = PH_PULL;
       }
@@ -496,13 +519,14 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
         // sources of the next stage: the blocked list of the last level, or,
         // when it outnumbers the remaining uncovered nodes, none: those
         // nodes pull from their assigned neighbours instead
-        if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && c.cnt[s.blk].v > c.cntU[s.ucur].v) s.pull = 1;
+        if (!s.pull && d.pull_mode == CLDIAM_PULL_AUTO && pull_pays(c, c.cntU[s.ucur].v)) s.pull = 1;
         if (!s.pull) { uint32_t t = s.fcur; s.fcur = s.blk; s.blk = t; }
         else c.cnt[s.fcur].v = 0;
       }
       // (synchronous steps: the active list, merged with the blocked list,
       // already holds them)
       c.cnt[s.blk].v = 0;
+      c.blk_arcs.v = 0;
       c.cnt[s.fnxt].v = 0;
       begin_stage(d, s, c, job.ctl);
       break;
@@ -644,6 +668,7 @@ struct Stage {
   uint32_t cnt[3];
   uint32_t base[3];
   unsigned long long acc;   // min (NEXT) or max (ASSIGN) accumulator
+  unsigned long long blk_arcs;   // RELAX: heavy arcs of the rows this workgroup put on the blocked list
   uint32_t acc32;           // centers drawn (SELECT)
   uint32_t flush;           // a list passed the flush threshold
   uint32_t fmin;            // RELAX: smallest distance pushed on the next frontier
@@ -796,8 +821,10 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
       if (lq) lq_push(lq_cnt, lq, v, d.lq_cap);
     }
   }
-  if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
+  if (blocked && job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id) {
     stage_push(S, out, 2, u);
+    atomicAdd(&S.blk_arcs, (unsigned long long)(deg - (int32_t)scanned));   // the light arcs come first
+  }
   return scanned;
 }
 
@@ -880,10 +907,12 @@ __device__ __forceinline__ void relax_one_sync(const Job &job, int64_t off, uint
   }
 }
 
-__device__ __forceinline__ void mark_blocked(const Job &job, int64_t off, int32_t u, uint32_t level_id, Stage &S,
-                                             const Out *out) {
-  if (job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id)
+__device__ __forceinline__ void mark_blocked(const Job &job, int64_t off, int32_t u, uint32_t level_id, int32_t heavy,
+                                             Stage &S, const Out *out) {
+  if (job.bstamp[off + u] != level_id && atomicExch(&job.bstamp[off + u], level_id) != level_id) {
     stage_push(S, out, 2, u);
+    atomicAdd(&S.blk_arcs, (unsigned long long)heavy);
+  }
 }
 
 // NEXT for a short row: smallest d_u + w over its heavy arcs (w > Delta - d_u)
@@ -977,18 +1006,23 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
     const uint32_t lim = delta - (uint32_t)(ku >> 32);
     if (mode != 1) {
       const int32_t start = resume ? resume_at_wave(job, off, u, ku, row, a1) : 0;
+      int32_t light_end = start;   // the light arcs are a prefix of the row
       for (int32_t base = start; base < a1; base += 64) {
         const int32_t a = base + (int32_t)lane;
         const uint64_t arc = a < a1 ? row[a] : ~0ull;
         const bool light = a < a1 && (uint32_t)(arc >> 32) <= lim;
-        if (!__any(light)) break;
+        const int nl = __popcll(__ballot(light));
+        light_end = base + nl;
+        if (nl == 0) break;
         if (light) {
           ++scanned;
           if (mode == 2) relax_one_sync(job, off, ku, arc, it, S, out);
           else relax_one(job, off, ku, arc, it, S, out, lq_cnt, lq, d.lq_cap);
         }
+        if (nl < 64) break;
       }
-      if (lane == 0 && (uint32_t)(row[a1 - 1] >> 32) > lim) mark_blocked(job, off, u, level_id, S, out);
+      if (lane == 0 && (uint32_t)(row[a1 - 1] >> 32) > lim)
+        mark_blocked(job, off, u, level_id, a1 - light_end, S, out);
       if (resume && lane == 0) note_scan(job, off, u, ku, lim);
     } else {
       // the heavy arcs start after the light prefix
@@ -1037,7 +1071,7 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
         if (mode == 2) relax_one_sync(job, off, ku, row[a], it, S, out);
         else relax_one(job, off, ku, row[a], it, S, out, lq_cnt, lq, d.lq_cap);
       }
-      if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, S, out);
+      if (threadIdx.x == 0 && lo < a1) mark_blocked(job, off, u, level_id, a1 - lo, S, out);
       // keep LDS staging within bounds between rows
       __syncthreads();
       // every thread's part of the row is done: record the scan
@@ -1079,10 +1113,18 @@ __device__ uint32_t coop_rows(const Job &job, const GDesc &d, int64_t off, uint3
 // instead: PULL gives an unreached node v the lexicographic minimum over its
 // neighbours u with a key of (d_u + w, c_u), d_u + w <= Delta (only v's own
 // thread writes v's key, so no atomic is needed); NEXT_PULL folds the smallest
-// d_u + w over the same arcs into S.acc.  Rows are sorted by weight, so PULL
-// stops past Delta (d_u >= 0) and NEXT_PULL once w reaches the best value.
+// d_u + w over the same arcs into S.acc.  Rows are sorted by weight, so both
+// stop early (pull_more).
 // A key read while its node is being pulled in the same pass is a real path
 // too, so taking it only moves the fixpoint closer.
+
+// Whether an arc of weight w, in a row sorted by weight, can still beat the
+// best offer: every offer over it is at least w (d_u >= 0), so PULL stops
+// past min(Delta, best distance) (an equal distance may still win on the
+// center id) and NEXT_PULL once w reaches the best distance.
+__device__ __forceinline__ bool pull_more(uint64_t w, uint64_t best, uint32_t delta, bool next) {
+  return next ? w < best : (w <= delta && w <= (best >> 32));
+}
 
 // Value of one arc (pull) or distance (next) offered to an unreached node.
 __device__ __forceinline__ uint64_t pull_offer(const Job &job, int64_t off, uint64_t arc, uint32_t delta, bool next) {
@@ -1123,7 +1165,7 @@ __device__ __forceinline__ void pull_item(const Job &job, const GDesc &d, int64_
 #pragma unroll
     for (int j = 0; j < kArcBatch; ++j) {
       const uint64_t w = arc[j] >> 32;
-      ok[j] = base + j < deg && (next ? w < best : w <= delta);
+      ok[j] = base + j < deg && pull_more(w, best, delta, next);
       if (base + j < deg && !ok[j]) stop = true;
     }
     uint64_t c[kArcBatch];
@@ -1162,7 +1204,7 @@ __device__ void pull_rows(const Job &job, const GDesc &d, int64_t off, uint32_t 
       const int32_t a = base + (int32_t)lane;
       const uint64_t arc = a < a1 ? row[a] : ~0ull;
       const uint64_t w = arc >> 32;
-      const bool in = a < a1 && (next ? w < best : w <= delta);
+      const bool in = a < a1 && pull_more(w, best, delta, next);
       if (!__any(in)) break;
       const uint64_t m = wave_min_all(in ? pull_offer(job, off, arc, delta, next) : CLD_INF64);
       best = m < best ? m : best;
@@ -1182,7 +1224,7 @@ __device__ void pull_rows(const Job &job, const GDesc &d, int64_t off, uint32_t 
       if (a < a1) {
         const uint64_t arc = row[a];
         const uint64_t w = arc >> 32;
-        if (next ? w < cur : w <= delta) {
+        if (pull_more(w, cur, delta, next)) {
           const uint64_t c = pull_offer(job, off, arc, delta, next);
           if (c < cur) atomicMin(&S.blk_min, (unsigned long long)c);
         }
@@ -1190,7 +1232,7 @@ __device__ void pull_rows(const Job &job, const GDesc &d, int64_t off, uint32_t 
       __syncthreads();
       const int32_t nxt = base + (int32_t)blockDim.x;
       const uint64_t cur2 = S.blk_min;
-      const bool stop = nxt >= a1 || (next ? (row[nxt] >> 32) >= cur2 : (row[nxt] >> 32) > delta);
+      const bool stop = nxt >= a1 || !pull_more(row[nxt] >> 32, cur2, delta, next);
       __syncthreads();   // every thread has read S.blk_min before the next chunk changes it
       if (stop) break;
     }
@@ -1287,6 +1329,7 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.out[1] = o[1];
     S.out[2] = o[2];
     S.acc = (phase == PH_NEXT || phase == PH_NEXT_PULL) ? CLD_INF64 : 0ull;
+    S.blk_arcs = 0;
     S.acc32 = 0;
     S.fmin = 0xffffffffu;
     S.lq_cnt[0] = 0;
@@ -1304,6 +1347,10 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
       switch (phase) {
         case PH_SELECT: {
           const int32_t v = job.U[ucur][off + idx];
+          if (stage == 0 && d.pull_mode == CLDIAM_PULL_AUTO) {
+            const uint32_t deg = (uint32_t)(d.row_ptr[v + 1] - d.row_ptr[v]);
+            if (deg > d.hub_deg) atomicAdd(&S.acc, (unsigned long long)deg);
+          }
           const uint32_t x0 = cld_philox_word0((uint32_t)v, stage, 0u, 0u, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
           if ((uint64_t)x0 < T) {
             job.key[off + v] = (uint64_t)(uint32_t)v;
@@ -1466,8 +1513,10 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     if ((phase == PH_NEXT || phase == PH_NEXT_PULL) && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
     if ((phase == PH_ASSIGN || phase == PH_C2_ASSIGN) && S.acc) atomicMax(&cn.radius.v, S.acc);
     if ((phase == PH_SELECT || phase == PH_C2_SELECT) && S.acc32) atomicAdd(&cn.centers.v, S.acc32);
+    if (phase == PH_SELECT && S.acc) atomicAdd(&cn.hub_arcs.v, S.acc);
     if (phase == PH_RELAX && S.fmin != 0xffffffffu) atomicMin(&cn.fmin.v, S.fmin);
     if (phase == PH_RELAX && steps && S.acc) atomicAdd(&cn.msgs.v, S.acc);
+    if (phase == PH_RELAX && S.blk_arcs) atomicAdd(&cn.blk_arcs.v, S.blk_arcs);
   }
   __syncthreads();
   return scanned;
@@ -1714,7 +1763,13 @@ int make_desc(const cldiam_graph &x, int g, const cldiam_tuning *tuning, GDesc *
     cld::set_error("decompose: unknown pull mode %d (graph %d)", pm, g);
     return CLDIAM_EINVAL;
   }
-  d.pull_mode = (uint32_t)pm;
+  // CLUSTER2 (its preliminary CLUSTER run included) and the literal steps never pull
+  d.pull_mode = d.variant == CLDIAM_VARIANT_FIXPOINT ? (uint32_t)pm : (uint32_t)CLDIAM_PULL_NEVER;
+  {
+    const int64_t hd = x.m / x.n * kHubDegree;
+    d.hub_deg = (uint32_t)(hd < 0xffffffffll ? hd : 0xffffffffll);
+    d.hub_min = (uint64_t)(x.m / kHubShare);
+  }
   if (tuning && tuning->local_rounds >= 0) d.local_rounds = tuning->local_rounds > 64 ? 64 : tuning->local_rounds;
   else if (x.m <= (int64_t)kDenseDegree * x.n) d.local_rounds = kLocalRounds;
   else d.local_rounds = x.n > kDenseLarge ? kLocalRoundsDense : 0;
