@@ -223,6 +223,9 @@ constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 constexpr uint32_t kPassChunk = kSweepThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
+constexpr uint32_t kRmaxSlots = 1024;   // RMAX: LDS table of cluster maxima (direct-mapped by center id)
+constexpr uint32_t kRmaxFree = 0xffffffffu;
+static_assert(kRmaxSlots == 1024, "RMAX slots are the top 10 bits of a 32-bit hash");
 constexpr uint32_t kPullArcs = 8;   // pull-mode switch: heavy blocked arcs per unreached node
 constexpr int64_t kHubDegree = 8;   // hub rows: more than kHubDegree x the average degree ...
 constexpr int64_t kHubShare = 8;    // ... holding more than 1/kHubShare of the arcs: pull from the first stage
@@ -655,7 +658,13 @@ struct Out {
 // LDS staging of up to three output lists of one graph run.
 struct Stage {
   int32_t buf[3][kStageCap];
-  int32_t lq[2][kLocalCap];  // local relaxation queues
+  union {
+    int32_t lq[2][kLocalCap];  // RELAX: local relaxation queues
+    struct {                   // RMAX: per-cluster maxima of this workgroup's nodes
+      uint32_t tag[kRmaxSlots];
+      unsigned long long mx[kRmaxSlots];
+    } rmax;
+  };
   uint32_t lq_cnt[2];
   int32_t mid[kMidCap];      // rows deferred to one wave each
   int32_t big[kBigCap];      // rows deferred to the whole workgroup
@@ -1337,6 +1346,12 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
     S.mid_cnt = 0;
     S.big_cnt = 0;
   }
+  if (phase == PH_RMAX) {
+    for (uint32_t t = threadIdx.x; t < kRmaxSlots; t += blockDim.x) {
+      S.rmax.tag[t] = kRmaxFree;
+      S.rmax.mx[t] = 0;
+    }
+  }
   __syncthreads();
   const Out *out = S.out;
   uint32_t scanned = 0;
@@ -1444,8 +1459,21 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
           if (k == CLD_INF64) break;
           const uint32_t c = (uint32_t)k;
           const uint64_t Dv = d.D[v];
-          uint64_t *rr = &job.R[off + c];
-          if (Dv > *rr) atomicMax((unsigned long long *)rr, (unsigned long long)Dv);
+          // a stage has few clusters: fold the maxima in LDS first (the slot
+          // of c, once claimed by c), in global memory when another center
+          // holds the slot
+          const uint32_t slot = (c * 2654435761u) >> 22;   // 10 bits: kRmaxSlots
+          uint32_t t = S.rmax.tag[slot];
+          if (t == kRmaxFree) {
+            t = atomicCAS(&S.rmax.tag[slot], kRmaxFree, c);
+            if (t == kRmaxFree) t = c;
+          }
+          if (t == c) {
+            if (Dv > S.rmax.mx[slot]) atomicMax(&S.rmax.mx[slot], (unsigned long long)Dv);
+          } else {
+            uint64_t *rr = &job.R[off + c];
+            if (Dv > *rr) atomicMax((unsigned long long *)rr, (unsigned long long)Dv);
+          }
           job.key[off + v] = (uint64_t)c;
           job.keyn[off + v] = (uint64_t)c;
           break;
@@ -1509,6 +1537,15 @@ __device__ uint32_t process_run(const Job &job, int g, uint32_t a, uint32_t b, u
   }
   if (nout) stage_flush(S, out, nout);
   __syncthreads();
+  if (phase == PH_RMAX) {
+    for (uint32_t t = threadIdx.x; t < kRmaxSlots; t += blockDim.x) {
+      const uint32_t c = S.rmax.tag[t];
+      if (c == kRmaxFree) continue;
+      uint64_t *rr = &job.R[off + c];
+      const unsigned long long m = S.rmax.mx[t];
+      if (m > *rr) atomicMax((unsigned long long *)rr, m);
+    }
+  }
   if (threadIdx.x == 0) {
     if ((phase == PH_NEXT || phase == PH_NEXT_PULL) && S.acc != CLD_INF64) atomicMin(&cn.next.v, S.acc);
     if ((phase == PH_ASSIGN || phase == PH_C2_ASSIGN) && S.acc) atomicMax(&cn.radius.v, S.acc);
