@@ -31,7 +31,8 @@ void *pinned_acquire(size_t bytes) {
     }
   }
   void *p = nullptr;
-  if (hipHostMalloc(&p, kPinnedBytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  // mapped and coherent: the host loops also poll words that kernels store into them
+  if (hipHostMalloc(&p, kPinnedBytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return nullptr;
   g_pinned_bytes += (int64_t)kPinnedBytes;
   return p;
 }

@@ -65,6 +65,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -197,6 +198,8 @@ struct Job {
   int32_t *C;
   int32_t G;
   int32_t nblocks;        // workgroups of a sweep launch
+  uint32_t *hmirror = nullptr;   // host-driven job: mapped pinned words {control steps done, done flag} that
+                                 // the host polls while it queues steps (nullptr: not mirrored)
   uint32_t cutoff;        // a workgroup ends its local rounds once this many workgroups have finished the
                           // sweep (the rounds are optional: every improved node is on the next frontier)
 };
@@ -644,6 +647,10 @@ __device__ void control_block(const Job &job) {
     ctl->sweep_id = sweep_id;
     ctl->iterations++;
     ctl->done = alldone;
+    if (job.hmirror) {
+      __hip_atomic_store(&job.hmirror[0], ctl->iterations, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&job.hmirror[1], alldone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
   __syncthreads();
 }
@@ -1711,7 +1718,9 @@ struct PtrArena {
   void *take(size_t n) { return (void *)a.take<T>(n); }
 };
 
-static_assert(sizeof(Ctl) <= cld::kPinnedBytes, "control block must fit a pooled pinned buffer");
+constexpr size_t kMirrorOffset = cld::kPinnedBytes - 128;   // host-loop mirror words in the readback buffer
+constexpr uint32_t kLeadSteps = 16;   // control + sweep steps the host queues ahead of the device
+static_assert(sizeof(Ctl) <= kMirrorOffset, "control block and mirror words must fit a pooled pinned buffer");
 
 // Workgroups of the sweep grid: one per CU unless requested (bounded by the
 // co-resident maximum for the persistent kernel).
@@ -1933,6 +1942,8 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
   cld::Pinned<Ctl> pinned;   // readback buffer, back to the pool when the call returns
   Ctl *hc = pinned.p;
   if (!hc) { cld::set_error("decompose: pinned host buffer allocation failed"); return CLDIAM_EHIP; }
+  // the last line of the same buffer: the control step's mirror for the host loop
+  volatile uint32_t *hm = (volatile uint32_t *)((char *)hc + kMirrorOffset);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   CLD_HIP(hipEventCreate(&ev0));
   CLD_HIP(hipEventCreate(&ev1));
@@ -1951,26 +1962,38 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     if (hc->timeout) { cld::set_error("decompose: grid barrier timed out"); return CLDIAM_ETIMEOUT; }
     if (!hc->done && !hc->error) { cld::set_error("decompose: persistent kernel ended early"); return CLDIAM_EHIP; }
   } else {
-    int batch = 4;
+    // The host queues control + sweep steps at most kLeadSteps ahead of the
+    // control steps the device has finished (read from the mapped mirror, no
+    // stream synchronisation), and stops queueing once the device reports the
+    // job done: only the steps already queued then run, and they return at once.
+    hm[0] = 0;
+    hm[1] = 0;
+    uint32_t *dm = nullptr;
+    CLD_HIP(hipHostGetDevicePointer((void **)&dm, (void *)hm, 0));
+    job.hmirror = dm;
     const auto t0 = std::chrono::steady_clock::now();
+    uint32_t queued = 0;
     for (;;) {
-      for (int i = 0; i < batch; ++i) {
+      if (hm[1]) break;
+      if (queued < hm[0] + kLeadSteps) {
         k_control<<<1, kThreads, 0, stream>>>(job);
         k_sweep<<<blocks, kSweepThreads, 0, stream>>>(job);
-      }
-      CLD_LAUNCH_CHECK("k_sweep");
-      CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-      CLD_HIP(hipStreamSynchronize(stream));
-      if (hc->done) {
-        CLD_HIP(hipEventRecord(ev1, stream));
-        break;
+        ++queued;
+        if ((queued & 15u) == 0) CLD_LAUNCH_CHECK("k_sweep");
+        continue;
       }
       if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(kJobSeconds + 30)) {
+        CLD_HIP(hipStreamSynchronize(stream));
         cld::set_error("decompose: host-driven job exceeded its time limit");
         return CLDIAM_ETIMEOUT;
       }
-      if (batch < 64) batch *= 2;
+      std::this_thread::yield();
     }
+    CLD_LAUNCH_CHECK("k_sweep");
+    CLD_HIP(hipEventRecord(ev1, stream));
+    CLD_HIP(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    CLD_HIP(hipStreamSynchronize(stream));
+    if (!hc->done) { cld::set_error("decompose: host-driven job ended without its done flag"); return CLDIAM_EHIP; }
     blocks = 0;
   }
   std::vector<GState> st(G);
