@@ -56,6 +56,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (first processor entry), for the CPU baseline."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def code_digest(path):
     """SHA-256 of a source file's code: comments, trailing spaces and blank
     lines removed, so that stored counters stay tied to the code they were
@@ -154,14 +165,19 @@ def step_bench(args, name):
                     f"tau={counts['tau']}, seed={counts['seed']}, once")
         tc0 = time.perf_counter()
         rdec = oracle.decompose(gs, counts["tau"], counts["seed"])
+        tc1 = time.perf_counter()
         rq = oracle.quotient(gs, rdec)
+        tc2 = time.perf_counter()
         rest = oracle.estimate(rq, rdec)
         tc = time.perf_counter() - tc0
         if gs is g:
             assert rest.phi_approx == counts["phi_approx"]
         cpu = {"value": round(gs.m // 2 / tc / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"{what} (decompose + quotient + estimate, {tc:.1f} s single-threaded, "
-                         f"host {os.cpu_count()} cpus visible)"}
+                         f"host {os.cpu_count()} cpus visible)",
+               "cpu_model": cpu_model(),
+               "phase_s": {"decompose": round(tc1 - tc0, 3), "quotient": round(tc2 - tc1, 3),
+                           "estimate": round(tc0 + tc - tc2, 3)}}
 
     src_sha = code_digest(os.path.join(HERE, "paper_1506_03265_amd", "csrc", "decompose.hip"))
     traffic = None
@@ -669,7 +685,8 @@ def sssp_bench(args):
         tc = time.perf_counter() - tc0
         assert rmx == best[2]
         cpu = {"value": round(counts["edges"] / tc / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"Dijkstra from the same source on the full workload ({tc:.1f} s single-threaded)"}
+               "sample": f"Dijkstra from the same source on the full workload ({tc:.1f} s single-threaded)",
+               "cpu_model": cpu_model()}
     t, bd, mx = best
     return {
         "metric": "Delta-stepping SSSP 2-approximation (the competitor), edges per second",
