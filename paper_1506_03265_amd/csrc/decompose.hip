@@ -814,7 +814,8 @@ __device__ __forceinline__ uint32_t relax_item(const Job &job, const GDesc &d, i
     // the same round trip, stamps the target for the next frontier.  The
     // stamp may be taken by an offer that then loses to a concurrent better
     // one; the node is then still on the frontier (harmless), and an improver
-    // never finds the node missing from it.
+    // never finds the node missing from it.  The returned stamp also keeps each
+    // node to one entry per list and sweep, which the lists' capacity (n) needs.
     bool front[kArcBatch];
 #pragma unroll
     for (int j = 0; j < kArcBatch; ++j) {
