@@ -587,9 +587,11 @@ __device__ void control_graph(const Job &job, int g, uint32_t sweep_id) {
   }
 }
 
-// One workgroup: control of every graph, then the next sweep's index space.
+// One workgroup of T threads: control of every graph, then the next sweep's
+// index space.
+template <int T>
 __device__ void control_block(const Job &job) {
-  __shared__ uint32_t scan[kThreads];
+  __shared__ uint32_t scan[T];
   __shared__ uint32_t carry, alldone;
   Ctl *ctl = job.ctl;
   uint32_t sweep_id = ctl->sweep_id + 1;
@@ -601,7 +603,7 @@ __device__ void control_block(const Job &job) {
     else if (now - ctl->t_start > ctl->t_limit && ctl->error == 0) atomicCAS(&ctl->error, 0u, (uint32_t)(-CLDIAM_ETIMEOUT));
   }
   __syncthreads();
-  for (int base = 0; base < job.G; base += kThreads) {
+  for (int base = 0; base < job.G; base += T) {
     int g = base + (int)threadIdx.x;
     uint32_t items = 0;
     if (g < job.G) {
@@ -628,7 +630,7 @@ __device__ void control_block(const Job &job) {
     }
     scan[threadIdx.x] = items;
     __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
+    for (int o = 1; o < T; o <<= 1) {
       uint32_t x = threadIdx.x >= (unsigned)o ? scan[threadIdx.x - o] : 0;
       __syncthreads();
       scan[threadIdx.x] += x;
@@ -636,7 +638,7 @@ __device__ void control_block(const Job &job) {
     }
     if (g < job.G) job.seg[g] = carry + scan[threadIdx.x] - items;
     __syncthreads();
-    if (threadIdx.x == kThreads - 1) carry += scan[kThreads - 1];
+    if (threadIdx.x == T - 1) carry += scan[T - 1];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -1642,7 +1644,17 @@ __global__ void __launch_bounds__(256) k_init_range(Job job, int64_t off, int32_
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_control(Job job) { control_block(job); }
+// A job of up to kSmallControl graphs takes a one-wave control step: no
+// cross-wave barriers, a 64-entry scan.
+template <int T>
+__global__ void __launch_bounds__(T) k_control(Job job) { control_block<T>(job); }
+
+constexpr int kSmallControl = 64;
+
+void launch_control(const Job &job, hipStream_t stream) {
+  if (job.G <= kSmallControl) k_control<kSmallControl><<<1, kSmallControl, 0, stream>>>(job);
+  else k_control<kThreads><<<1, kThreads, 0, stream>>>(job);
+}
 
 __global__ void __launch_bounds__(kSweepThreads) k_sweep(Job job) {
   __shared__ Stage S;
@@ -1654,7 +1666,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_persistent(Job job) {
   __shared__ Stage S;
   const uint32_t nb = gridDim.x;
   for (;;) {
-    if (blockIdx.x == 0) control_block(job);
+    if (blockIdx.x == 0) control_block<kSweepThreads>(job);
     if (!cld_grid_barrier(&job.ctl->bar, &job.ctl->timeout, nb)) return;
     if (job.ctl->done || job.ctl->timeout) return;
     sweep(job, blockIdx.x, nb, S);
@@ -1977,7 +1989,7 @@ extern "C" int cldiam_decompose_batch(int32_t G, const cldiam_graph *gs, cldiam_
     for (;;) {
       if (hm[1]) break;
       if (queued < hm[0] + kLeadSteps) {
-        k_control<<<1, kThreads, 0, stream>>>(job);
+        launch_control(job, stream);
         k_sweep<<<blocks, kSweepThreads, 0, stream>>>(job);
         ++queued;
         if ((queued & 15u) == 0) CLD_LAUNCH_CHECK("k_sweep");
@@ -2219,7 +2231,7 @@ extern "C" int cldiam_server_step(cldiam_server *s, int32_t max_sweeps, int32_t 
   if (nactive > 0 && max_sweeps > 0) {
     CLD_HIP(hipMemsetAsync(&job.ctl->iterations, 0, sizeof(uint32_t), stream));
     for (int i = 0; i < max_sweeps; ++i) {
-      k_control<<<1, kThreads, 0, stream>>>(job);
+      launch_control(job, stream);
       k_sweep<<<s->blocks, kSweepThreads, 0, stream>>>(job);
     }
     CLD_LAUNCH_CHECK("k_sweep");
