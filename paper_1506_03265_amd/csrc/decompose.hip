@@ -226,6 +226,8 @@ constexpr uint32_t kSmallFrontier = 1u << 15;   // frontiers up to this size get
 constexpr int kSmallRounds = 16;
 constexpr int kJobSeconds = 60;   // device-side limit of one decomposition job
 constexpr uint32_t kPassChunk = kSweepThreads;   // smallest chunk of a node pass (SELECT, ASSIGN, ...)
+constexpr uint32_t kBatchGrowChunk = kSweepThreads;        // jobs of several graphs: smallest growth chunk
+constexpr uint32_t kBatchPassChunk = 16 * kSweepThreads;   // ... and smallest node-pass chunk (items)
 constexpr uint32_t kRmaxSlots = 1024;   // RMAX: LDS table of cluster maxima (direct-mapped by center id)
 constexpr uint32_t kRmaxFree = 0xffffffffu;
 static_assert(kRmaxSlots == 1024, "RMAX slots are the top 10 bits of a 32-bit hash");
@@ -593,40 +595,63 @@ template <int T>
 __device__ void control_block(const Job &job) {
   __shared__ uint32_t scan[T];
   __shared__ uint32_t carry, alldone;
+  __shared__ unsigned long long work;
   Ctl *ctl = job.ctl;
   uint32_t sweep_id = ctl->sweep_id + 1;
   if (threadIdx.x == 0) {
     carry = 0;
     alldone = 1;
+    work = 0;
     const unsigned long long now = wall_clock64();
     if (ctl->iterations == 0) ctl->t_start = now;
     else if (now - ctl->t_start > ctl->t_limit && ctl->error == 0) atomicCAS(&ctl->error, 0u, (uint32_t)(-CLDIAM_ETIMEOUT));
   }
   __syncthreads();
+  // every graph's transition and the items of its next sweep
   for (int base = 0; base < job.G; base += T) {
-    int g = base + (int)threadIdx.x;
-    uint32_t items = 0;
+    const int g = base + (int)threadIdx.x;
     if (g < job.G) {
       if (ctl->error == 0 || job.st[g].phase == PH_DONE) control_graph(job, g, sweep_id);
       if (ctl->error != 0 && job.st[g].phase != PH_DONE) job.st[g].phase = PH_DONE;
       const uint32_t phase = job.st[g].phase;
       const uint32_t n_items =
           job.st[g].phase == PH_C2_INIT ? (uint32_t)job.desc[g].n : items_of(job.st[g], job.cn[g]);
-      // Every graph is cut into its own chunks, at most chunk_factor per
-      // workgroup, so that the frontier of each graph is spread over the whole
-      // grid whatever the other graphs of the job are doing (a node pass of
-      // millions of cheap items beside a small frontier of costly rows).
+      job.seg[2 * job.G + 1 + g] = n_items;
+      if (n_items) atomicAdd(&work, (unsigned long long)n_items);
+      if (phase != PH_DONE && phase != PH_IDLE) atomicAnd(&alldone, 0u);
+    }
+  }
+  __syncthreads();
+  // In a job of several graphs no chunk is smaller than the sweep's average
+  // items per workgroup (up to kBatchGrowChunk / kBatchPassChunk): a small
+  // frontier or node list then takes a few larger chunks instead of one per
+  // workgroup, each of which would pay a chunk's fixed cost (setup,
+  // barriers, local rounds) for a handful of items.
+  const unsigned long long avg = work / (unsigned long long)job.nblocks;
+  for (int base = 0; base < job.G; base += T) {
+    const int g = base + (int)threadIdx.x;
+    uint32_t items = 0;
+    if (g < job.G) {
+      const uint32_t phase = job.st[g].phase;
+      const uint32_t n_items = job.seg[2 * job.G + 1 + g];
+      // Otherwise every graph is cut into its own chunks, at most chunk_factor
+      // per workgroup, so that the frontier of each graph is spread over the
+      // whole grid whatever the other graphs of the job are doing (a node pass
+      // of millions of cheap items beside a small frontier of costly rows).
       uint32_t per = 0;
       if (n_items) {
         const bool grow = phase == PH_RELAX || phase == PH_NEXT || phase == PH_PULL || phase == PH_NEXT_PULL;
         const uint32_t nch = (uint32_t)job.nblocks * (grow ? (uint32_t)job.desc[g].chunk_factor : 1u);
         per = (n_items + nch - 1) / nch;
         if (!grow && per < kPassChunk) per = kPassChunk;
+        if (job.G > 1) {
+          const unsigned long long cap = grow ? kBatchGrowChunk : kBatchPassChunk;
+          const uint32_t least = (uint32_t)(avg < cap ? avg : cap);
+          if (per < least) per = least;
+        }
         items = (n_items + per - 1) / per;
       }
       job.seg[job.G + 1 + g] = per;
-      job.seg[2 * job.G + 1 + g] = n_items;
-      if (phase != PH_DONE && phase != PH_IDLE) atomicAnd(&alldone, 0u);
     }
     scan[threadIdx.x] = items;
     __syncthreads();
