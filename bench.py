@@ -120,15 +120,19 @@ def step_bench(args, name):
         td = time.perf_counter()
         return st, q, est, (tb - ta, tc - tb, td - tc)
 
+    def check(st, q, est):
+        ok = (st.num_clusters == counts["num_clusters"] and st.stages == counts["stages"]
+              and st.delta_end == counts["delta_end"] and st.radius == counts["radius"]
+              and (args.decompose_only or (q.k == counts["quotient_k"] and est[1] == counts["phi_approx"])))
+        if not ok:
+            log("[bench] result differs from the stored oracle values", st, est)
+            sys.exit(1)
+
     for i in range(args.warmup):
         st, q, est, _ = step()
         log(f"[bench] warmup {i}: kernel {st.kernel_ms:.2f} ms, sweeps {st.sweeps}, iterations {st.iterations}")
-    ok = (st.num_clusters == counts["num_clusters"] and st.stages == counts["stages"]
-          and st.delta_end == counts["delta_end"] and st.radius == counts["radius"]
-          and (args.decompose_only or (q.k == counts["quotient_k"] and est[1] == counts["phi_approx"])))
-    if not ok:
-        log("[bench] result differs from the stored oracle values", st, est)
-        sys.exit(1)
+    if args.warmup:
+        check(st, q, est)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -138,6 +142,7 @@ def step_bench(args, name):
         kms.append(st.kernel_ms)
         phases.append(ph)
     torch.cuda.synchronize()
+    check(st, q, est)
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
     edges = counts["edges"]
