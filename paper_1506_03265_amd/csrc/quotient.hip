@@ -80,7 +80,7 @@ __global__ void k_center_list(const int32_t *cluster, int32_t n, const uint32_t 
 // memory: the table is written out, with one global reservation, whenever it
 // is half full after a round and at the end.  A pair that finds no slot after
 // a few probes goes straight to global memory.
-constexpr int kEmitThreads = 256;
+constexpr int kEmitThreads = 1024;
 constexpr int kEmitThreadDeg = 16;
 constexpr int kEmitBlockDeg = 4096;
 constexpr int kEmitDefer = 512;     // deferred rows per round
@@ -139,6 +139,30 @@ __device__ void hash_flush(EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *c
   __syncthreads();
 }
 
+// One pending pair per thread, in registers.  A stage has few clusters, so
+// consecutive arcs of a row mostly lead to the same cluster: their pairs fold
+// here and only a change of key touches the LDS table (whose random slots
+// cost bank conflicts).  Flushed at the end of each row part.
+struct PairCache {
+  uint64_t key = ~0ull, val = ~0ull;
+};
+
+__device__ __forceinline__ void cache_pair(PairCache &pc, uint64_t key, uint64_t val, EmitState &E, uint64_t *keys,
+                                           uint64_t *vals, QCtl *ctl) {
+  if (key == pc.key) {
+    if (val < pc.val) pc.val = val;
+    return;
+  }
+  if (pc.key != ~0ull) emit_pair(E, pc.key, pc.val, keys, vals, ctl);
+  pc.key = key;
+  pc.val = val;
+}
+
+__device__ __forceinline__ void cache_flush(PairCache &pc, EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
+  if (pc.key != ~0ull) emit_pair(E, pc.key, pc.val, keys, vals, ctl);
+  pc.key = ~0ull;
+}
+
 // Node-side inputs of the emission: either cluster ids, D and the dense
 // numbering, or the packed words of k_pack_nodes.
 struct NodeIn {
@@ -168,15 +192,15 @@ __device__ __forceinline__ void node_of(const NodeIn &in, int32_t u, int kb, uin
 
 template <bool kPacked>
 __device__ __forceinline__ void emit_arc(uint64_t arc, uint32_t cu, uint64_t du, uint64_t ka, const NodeIn &in,
-                                         EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
+                                         PairCache &pc, EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
   const int32_t v = (int32_t)(uint32_t)arc;
   if (kPacked) {
     const uint64_t x = in.pk[v];
     const uint32_t cv = (uint32_t)(x >> in.lb);
-    if (cv != cu) emit_pair(E, ka | (uint64_t)cv, (arc >> 32) + du + (x & ((1ull << in.lb) - 1ull)), keys, vals, ctl);
+    if (cv != cu) cache_pair(pc, ka | (uint64_t)cv, (arc >> 32) + du + (x & ((1ull << in.lb) - 1ull)), E, keys, vals, ctl);
   } else {
     const int32_t cv = in.cluster[v];
-    if ((uint32_t)cv != cu) emit_pair(E, ka | (uint64_t)in.dense[cv], (arc >> 32) + du + in.D[v], keys, vals, ctl);
+    if ((uint32_t)cv != cu) cache_pair(pc, ka | (uint64_t)in.dense[cv], (arc >> 32) + du + in.D[v], E, keys, vals, ctl);
   }
 }
 
@@ -208,7 +232,9 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
         uint64_t du, ka;
         node_of<kPacked>(in, (int32_t)u, kb, &cu, &du, &ka);
         const uint64_t *row = arcs + a0;
-        for (int32_t a = 0; a < deg; ++a) emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
+        PairCache pc;
+        for (int32_t a = 0; a < deg; ++a) emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+        cache_flush(pc, E, keys, vals, ctl);
       }
     }
     __syncthreads();
@@ -221,8 +247,10 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
+      PairCache pc;
       for (int32_t a = (int32_t)lane; a < deg; a += 64)
-        emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
+        emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+      cache_flush(pc, E, keys, vals, ctl);
     }
     const uint32_t nbg = E.nbig < kEmitDefer ? E.nbig : kEmitDefer;
     for (uint32_t i = 0; i < nbg; ++i) {
@@ -233,8 +261,10 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
+      PairCache pc;
       for (int32_t a = (int32_t)threadIdx.x; a < deg; a += (int32_t)blockDim.x)
-        emit_arc<kPacked>(row[a], cu, du, ka, in, E, keys, vals, ctl);
+        emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+      cache_flush(pc, E, keys, vals, ctl);
       __syncthreads();
       if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
     }
