@@ -190,18 +190,32 @@ __device__ __forceinline__ void node_of(const NodeIn &in, int32_t u, int kb, uin
   }
 }
 
+// The graph is symmetric with equal weights both ways and w + D_u + D_v is
+// symmetric, so each edge is taken once, from its smaller end (u < v), and
+// gives both directed pairs: half the far-end gathers of walking every arc.
+// pc folds the pairs out of u's cluster, rc those into it.
 template <bool kPacked>
-__device__ __forceinline__ void emit_arc(uint64_t arc, uint32_t cu, uint64_t du, uint64_t ka, const NodeIn &in,
-                                         PairCache &pc, EmitState &E, uint64_t *keys, uint64_t *vals, QCtl *ctl) {
+__device__ __forceinline__ void emit_arc(uint64_t arc, int32_t u, uint32_t cu, uint64_t du, uint64_t ka, int kb,
+                                         const NodeIn &in, PairCache &pc, PairCache &rc, EmitState &E,
+                                         uint64_t *keys, uint64_t *vals, QCtl *ctl) {
   const int32_t v = (int32_t)(uint32_t)arc;
+  if (v < u) return;
+  const uint64_t da = ka >> kb;   // dense index of u's cluster
+  uint64_t db, val;
   if (kPacked) {
     const uint64_t x = in.pk[v];
     const uint32_t cv = (uint32_t)(x >> in.lb);
-    if (cv != cu) cache_pair(pc, ka | (uint64_t)cv, (arc >> 32) + du + (x & ((1ull << in.lb) - 1ull)), E, keys, vals, ctl);
+    if (cv == cu) return;
+    db = cv;
+    val = (arc >> 32) + du + (x & ((1ull << in.lb) - 1ull));
   } else {
     const int32_t cv = in.cluster[v];
-    if ((uint32_t)cv != cu) cache_pair(pc, ka | (uint64_t)in.dense[cv], (arc >> 32) + du + in.D[v], E, keys, vals, ctl);
+    if ((uint32_t)cv == cu) return;
+    db = in.dense[cv];
+    val = (arc >> 32) + du + in.D[v];
   }
+  cache_pair(pc, ka | db, val, E, keys, vals, ctl);
+  cache_pair(rc, (db << kb) | da, val, E, keys, vals, ctl);
 }
 
 template <bool kPacked>
@@ -232,9 +246,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
         uint64_t du, ka;
         node_of<kPacked>(in, (int32_t)u, kb, &cu, &du, &ka);
         const uint64_t *row = arcs + a0;
-        PairCache pc;
-        for (int32_t a = 0; a < deg; ++a) emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+        PairCache pc, rc;
+        for (int32_t a = 0; a < deg; ++a)
+          emit_arc<kPacked>(row[a], (int32_t)u, cu, du, ka, kb, in, pc, rc, E, keys, vals, ctl);
         cache_flush(pc, E, keys, vals, ctl);
+        cache_flush(rc, E, keys, vals, ctl);
       }
     }
     __syncthreads();
@@ -247,10 +263,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
-      PairCache pc;
+      PairCache pc, rc;
       for (int32_t a = (int32_t)lane; a < deg; a += 64)
-        emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+        emit_arc<kPacked>(row[a], u, cu, du, ka, kb, in, pc, rc, E, keys, vals, ctl);
       cache_flush(pc, E, keys, vals, ctl);
+      cache_flush(rc, E, keys, vals, ctl);
     }
     const uint32_t nbg = E.nbig < kEmitDefer ? E.nbig : kEmitDefer;
     for (uint32_t i = 0; i < nbg; ++i) {
@@ -261,10 +278,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const int64_t *rp, const 
       uint32_t cu;
       uint64_t du, ka;
       node_of<kPacked>(in, u, kb, &cu, &du, &ka);
-      PairCache pc;
+      PairCache pc, rc;
       for (int32_t a = (int32_t)threadIdx.x; a < deg; a += (int32_t)blockDim.x)
-        emit_arc<kPacked>(row[a], cu, du, ka, in, pc, E, keys, vals, ctl);
+        emit_arc<kPacked>(row[a], u, cu, du, ka, kb, in, pc, rc, E, keys, vals, ctl);
       cache_flush(pc, E, keys, vals, ctl);
+      cache_flush(rc, E, keys, vals, ctl);
       __syncthreads();
       if (E.used > kHashCap / 2) hash_flush(E, keys, vals, ctl);
     }
