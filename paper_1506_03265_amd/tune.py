@@ -7,8 +7,8 @@ distance-bucket widths of the relaxation sweeps (all nodes, and nodes with
 long rows: the Delta of the Delta-stepping-style order, not the algorithm's
 initial Delta, which changes results), the number of growth chunks per
 workgroup, the threads per row (rows above a degree go to a wave of 64
-threads, above another to the whole workgroup) and the queue tile of the
-local rounds.  Each
+threads, above another to the whole workgroup), the queue tile of the
+local rounds and when growth pulls from the unreached side.  Each
 candidate is timed on the job itself; the outputs of every candidate are
 checked to be identical to the first one's (a schedule that changed a result
 would be a bug).  The choice is cached per workload class (graph count and
@@ -21,7 +21,7 @@ import math
 import os
 import time
 
-from . import DRIVER_HOST, DRIVER_PERSISTENT, DecomposeJob, _torch
+from . import DRIVER_HOST, DRIVER_PERSISTENT, PULL_ALWAYS, PULL_NEVER, DecomposeJob, _torch
 
 CANDIDATES = (
     [dict(driver=DRIVER_HOST, local_rounds=r, grid_blocks=0) for r in (0, 2, 4, 8)]
@@ -33,6 +33,7 @@ CANDIDATES = (
     + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, local_queue=q) for q in (512,)]
     + [dict(driver=DRIVER_HOST, local_rounds=r, grid_blocks=0, local_cutoff=c) for r, c in ((16, 100), (8, 90),
                                                                                           (16, 50))]
+    + [dict(driver=DRIVER_HOST, local_rounds=8, grid_blocks=0, pull_mode=p) for p in (PULL_NEVER, PULL_ALWAYS)]
     + [dict(driver=DRIVER_HOST, local_rounds=4, grid_blocks=128)]
     + [dict(driver=DRIVER_PERSISTENT, local_rounds=r, grid_blocks=128) for r in (0, 4)]
 )
